@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the two-component D3Q19 Shan-Chen step on one MI355X.
+
+One step = one call of lb_step(1): densities and pseudopotentials, force,
+velocity-shifted BGK collision, streaming, for both components of every
+node.  Default workload: the 256^3 periodic spinodal lattice in float64
+(tau = 0.8, G = 3.5, rho_A, rho_B = 1 +- 0.02 uniform noise).  GLUPS counts
+nodes, solid or not, per second (Eq. glups of the paper).
+
+Prints one JSON line.  Inputs are synthetic and already resident in HBM when
+the timed region starts.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "GLUPS & % HBM roofline, 2-comp D3Q19 256^3; adjoint/forward time ratio"
+BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2}
+KERNEL_SOURCES = ["paper_2112_08264_amd/csrc/lb_device.h", "paper_2112_08264_amd/csrc/lb_kernels.h",
+                  "paper_2112_08264_amd/csrc/lb_api.hip"]
+
+
+def algorithmic_bytes_per_lup(storage: str) -> int:
+    """Both components' 19 populations read once and written once."""
+    return 2 * 19 * 2 * BYTES_PER_VALUE[storage]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, timing_slots=True):
+    """Run one storage form; return a dict of timings."""
+    a, b = fields
+    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0)
+    try:
+        lat.set_fields(a, b)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        tot0, _ = lat.totals()
+        P.lb_timing(lat.ctx, timing_slots)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record()
+        lat.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+        ev_ms = e0.elapsed_time(e1)
+        kernels = {}
+        for s in range(P.lb_timing_slots()):
+            ms, cnt = P.lb_timing_read(lat.ctx, s)
+            if cnt:
+                kernels[P.lb_timing_name(s)] = {"avg_ms": ms / cnt, "launches": cnt}
+        P.lb_timing(lat.ctx, False)
+        tot1, nonfinite = lat.totals()
+    finally:
+        lat.close()
+    mass_drift = max(abs(tot1[k] - tot0[k]) / abs(tot0[k]) for k in range(2))
+    return {"event_ms": ev_ms, "wall_ms": (w1 - w0) * 1e3, "kernels": kernels, "nonfinite": nonfinite,
+            "mass_drift": mass_drift}
+
+
+def cpu_baseline(w, fields_fn):
+    """The FP64 oracle on the host, on a slab of the same lattice (bounded CPU time)."""
+    import numpy as np
+
+    from oracle import lb_oracle as O
+
+    nz, ny, nx = w.shape
+    planes = min(nz, 48)
+    steps = 2
+    a, b = fields_fn()
+    a = np.ascontiguousarray(a.reshape(w.shape)[:planes])
+    b = np.ascontiguousarray(b.reshape(w.shape)[:planes])
+    f = O.init_equilibrium(a, b)
+    p = O.Params(w.tau, w.G)
+    t0 = time.perf_counter()
+    f = O.step(f, p, n=steps)
+    dt = time.perf_counter() - t0
+    nodes = planes * ny * nx
+    return {
+        "value": nodes * steps / dt / 1e9,
+        "unit": "GLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} steps of the float64 NumPy oracle on a {nx}x{ny}x{planes} slab of the {w.name} "
+                  f"initial state ({nodes} of {w.nodes} nodes, {dt:.1f} s; NumPy elementwise work is "
+                  f"single-threaded; host has {os.cpu_count()} logical CPUs)",
+    }
+
+
+def traffic_from_profile(kernel: str, workload: str, lups_per_launch: int):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data[workload][kernel]
+    except (KeyError, ValueError):
+        return None
+    if ent.get("source_digest") != source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="spinodal256_f64")
+    ap.add_argument("--form-steps", type=int, default=200, help="timed steps of the float32 / float16 forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2112_08264_amd as P
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    P.library()  # raises if liblb.so is missing: there is no fallback
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    log(f"bench: workload {w.name} {w.shape} storage {w.storage}; generating inputs")
+    a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+    fields = (a.reshape(-1), b.reshape(-1))
+
+    log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
+    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields)
+    ms_step = main_run["event_ms"] / args.steps
+    glups = w.nodes / (ms_step * 1e-3) / 1e9
+    bpl = algorithmic_bytes_per_lup(w.storage)
+    log(f"bench: {ms_step:.3f} ms/step, {glups:.3f} GLUPS, kernels {main_run['kernels']}")
+
+    # dominant kernel: the one with the largest summed time
+    kernels = main_run["kernels"]
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    dom_ms = kernels[dom]["avg_ms"]
+    achieved = bpl * w.nodes / (dom_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(dom, w.name, w.nodes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "algorithmic_bytes_per_lup": bpl, "lups_per_launch": w.nodes}
+
+    forms = {}
+    if not args.no_forms:
+        for st in ("f32", "f16s"):
+            if st == w.storage:
+                continue
+            log(f"bench: form {st}, {args.form_steps} steps")
+            r = time_form(P, torch, w, st, args.form_steps, 10, fields)
+            ms = r["event_ms"] / args.form_steps
+            g = w.nodes / (ms * 1e-3) / 1e9
+            forms[st] = {"glups": round(g, 4), "ms_per_step": round(ms, 4),
+                         "step_hbm_frac": round(algorithmic_bytes_per_lup(st) * g / HBM_PEAK_GBS, 4),
+                         "vs_f64": round(g / glups, 3) if w.storage == "f64" else None,
+                         "nonfinite": r["nonfinite"], "kernels": r["kernels"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        cpu = cpu_baseline(w, lambda: (a, b))
+
+    out = {
+        "metric": METRIC,
+        "value": round(glups, 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.storage,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(reversed(w.shape)), "storage": w.storage,
+                   "tau": list(w.tau), "G": w.G, "rho0": list(w.rho0), "noise": w.amp, "seed": w.seed,
+                   "boundary": "periodic", "solid_spheres": w.spheres},
+        "step_hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "adjoint_forward_ratio": None,
+        "mass_drift": main_run["mass_drift"],
+        "nonfinite": main_run["nonfinite"],
+        "wall_ms": round(main_run["wall_ms"], 2),
+        "kernel_source_digest": source_digest(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,159 @@
+/*
+ * lb.h - C ABI of liblb: the two-component D3Q19 Shan-Chen lattice-Boltzmann
+ * step on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv:2112.08264):
+ *   - D3Q19 lattice: the rest velocity, 6 axis neighbours and 12 face
+ *     diagonals (Sec. 2); weights 1/3, 1/18, 1/36 (Appendix, D3Q19 table).
+ *   - Two population sets f_i^k, k in {A, B}; rho_k = sum_i f_i^k and the
+ *     mixture momentum sum_k sum_i f_i^k c_i (Appendix, two-component LBE).
+ *   - BGK relaxation f* = (1 - omega_k) f + omega_k f^eq, omega_k = 1/tau_k
+ *     (Sec. 2, Eq. 1), viscosity c_s^2 (tau - 1/2) (Eq. 2), with the
+ *     second-order equilibrium of Eq. LEQ (Appendix), c_s^2 = 1/3.
+ *   - Streaming f_i(x + c_i, t + 1) = f*_i(x, t) (Eq. 1), periodic box, and
+ *     halfway bounce-back at solid nodes at rest (Appendix, Eq. LADDFLBE
+ *     with zero wall velocity).
+ *   - Inter-component Shan-Chen force (not in the paper, which uses colour
+ *     gradient): F_k(x) = -G psi_k(x) sum_{i=1..18} w_i psi_kbar(x + c_i) c_i,
+ *     psi = rho_ref (1 - exp(-rho / rho_ref)), applied by shifting the
+ *     equilibrium velocity of component k to
+ *       v_k = u' + tau_k F_k / rho_k,
+ *       u'  = (sum_k m_k / tau_k) / (sum_k rho_k / tau_k),  m_k = sum_i f_i^k c_i.
+ *
+ * Conventions shared by every call:
+ *   - Node index n = x + nx * (y + ny * z), x fastest.  N = nx * ny * nz.
+ *   - Population index order i = 0..18:
+ *       0 (0,0,0); 1 (+1,0,0); 2 (-1,0,0); 3 (0,+1,0); 4 (0,-1,0);
+ *       5 (0,0,+1); 6 (0,0,-1); 7 (+1,+1,0); 8 (-1,-1,0); 9 (+1,-1,0);
+ *       10 (-1,+1,0); 11 (+1,0,+1); 12 (-1,0,-1); 13 (+1,0,-1);
+ *       14 (-1,0,+1); 15 (0,+1,+1); 16 (0,-1,-1); 17 (0,+1,-1); 18 (0,-1,+1).
+ *   - Population arrays exchanged through this ABI are float64
+ *     [k][i][n] (k = A then B), 2 * 19 * N values, no padding; they hold the
+ *     pre-collision state f(t) (the state the next step starts from).
+ *   - Field arrays are float64 [n]; velocity arrays are float64 [3][n]
+ *     (u_x plane, then u_y, then u_z); the solid mask is uint8 [n], nonzero
+ *     meaning solid.
+ *   - on_device != 0: the pointer is device memory of the context's device;
+ *     on_device == 0: host memory.  The caller owns every array it passes;
+ *     the library copies what it needs before returning (host inputs) or
+ *     before the enqueued work completes (device inputs, stream-ordered).
+ *   - Every call returns an lb_status and never aborts the process.
+ *   - Work is enqueued on the context's stream.  lb_step returns without
+ *     waiting; lb_set_fields, lb_set_populations, lb_moments,
+ *     lb_get_populations and lb_totals return after their results are
+ *     complete.  One context must not be used from two threads at once.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+
+typedef struct lb_ctx lb_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  LB_OK = 0,
+  LB_EINVAL = -1,     /* bad argument: NULL pointer, size, tau <= 1/2, non-finite or negative input */
+  LB_ENOMEM = -2,     /* device allocation failed */
+  LB_EDEVICE = -3,    /* a HIP runtime call failed, or no usable device */
+  LB_ESTATE = -4,     /* call out of order: no fields set yet */
+  LB_ENONFINITE = -5  /* the state holds NaN or Inf */
+} lb_status;
+
+typedef enum {
+  LB_F64 = 0,          /* populations stored as float64, float64 arithmetic */
+  LB_F32 = 1,          /* stored as float32, float32 arithmetic */
+  LB_F16_SHIFTED = 2   /* stored as float16 h = f - w_i rho0_k, float32 arithmetic */
+} lb_storage;
+
+typedef struct {
+  int32_t nx, ny, nz;   /* periodic box, each >= 1; no tile-size restriction */
+  double tau[2];        /* relaxation time per component, > 1/2 (Eq. 2: 0 < omega < 2) */
+  double G;             /* Shan-Chen coupling; G > 0 pushes the components apart */
+  double psi_ref;       /* rho_ref of the pseudopotential, > 0 (1.0 in the standard form) */
+  double rho0[2];       /* reference density per component for LB_F16_SHIFTED; ignored otherwise */
+  int32_t storage;      /* lb_storage */
+  int32_t device;       /* HIP device ordinal */
+  void* stream;         /* hipStream_t the work is enqueued on; NULL = the null stream */
+} lb_params;
+
+/* Fill *p with defaults: 1^3 box, tau = 1, G = 0, psi_ref = 1, rho0 = 1,
+ * LB_F64, device 0, null stream. */
+void lb_params_default(lb_params* p);
+
+/* Validate *params, allocate the two population grids (A/B ping-pong) and
+ * the work buffers on params->device, and return a context in *out.
+ * Errors: LB_EINVAL (NULL, nx/ny/nz < 1, tau <= 1/2 or non-finite,
+ * psi_ref <= 0, unknown storage, N * 38 overflowing 2^62), LB_EDEVICE (bad
+ * device), LB_ENOMEM.  On error *out is set to NULL. */
+lb_status lb_create(const lb_params* params, lb_ctx** out);
+
+/* Wait for the context's work, free its device memory and the context.
+ * NULL is accepted and ignored. */
+lb_status lb_destroy(lb_ctx* ctx);
+
+/* Replace the stream later calls enqueue on (NULL = null stream). */
+lb_status lb_set_stream(lb_ctx* ctx, void* stream);
+
+/* Initial state f_i^k(x) = f_i^eq(rho_k(x), u(x)) (Eq. LEQ), zero at solid
+ * nodes.  rho_a, rho_b: [N], finite and >= 0.  u: [3][N] finite, or NULL
+ * for a fluid at rest.  solid: [N] mask or NULL for none; the mask is kept
+ * for every later step.  Errors: LB_EINVAL, LB_EDEVICE, LB_ENOMEM. */
+lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b,
+                        const double* u, const uint8_t* solid, int on_device);
+
+/* Advance n >= 0 steps.  One step: densities rho_k and pseudopotentials,
+ * force, velocity-shifted BGK collision, pull streaming with bounce-back at
+ * solid neighbours.  Enqueued; returns before completion.  Errors: LB_EINVAL
+ * (n < 0), LB_ESTATE (no lb_set_fields / lb_set_populations yet), LB_EDEVICE. */
+lb_status lb_step(lb_ctx* ctx, int32_t n);
+
+/* Moments of the current state: rho_a, rho_b [N] and the barycentric
+ * velocity u = (m_A + m_B + (F_A + F_B) / 2) / (rho_A + rho_B) as [3][N]
+ * (zero at solid nodes).  Any output pointer may be NULL to skip it.
+ * Errors: LB_EINVAL, LB_ESTATE, LB_EDEVICE. */
+lb_status lb_moments(lb_ctx* ctx, double* rho_a, double* rho_b, double* u, int on_device);
+
+/* Copy out / replace the pre-collision populations, float64 [2][19][N].
+ * lb_set_populations encodes into the context's storage format and zeroes
+ * solid nodes.  Errors: LB_EINVAL, LB_ESTATE (get before any state),
+ * LB_EDEVICE. */
+lb_status lb_get_populations(lb_ctx* ctx, double* f, int on_device);
+lb_status lb_set_populations(lb_ctx* ctx, const double* f, int on_device);
+
+/* Conserved totals of the current state, accumulated in float64 on the
+ * device with a fixed reduction order (bitwise repeatable):
+ * out[0] = sum_x rho_A, out[1] = sum_x rho_B, out[2..4] = sum_x sum_k m_k.
+ * *nonfinite = 1 if any population is NaN or Inf (and the call then returns
+ * LB_ENONFINITE), else 0.  Errors: LB_EINVAL, LB_ESTATE, LB_EDEVICE. */
+lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite);
+
+/* Per-kernel timing with HIP events recorded around every launch on the
+ * context's stream.  lb_timing(ctx, 1) starts a fresh record, 0 stops
+ * recording.  lb_timing_read waits for the stream and returns, for kernel
+ * slot k (0 <= k < lb_timing_slots()), the summed duration in milliseconds
+ * and the launch count; lb_timing_name gives the slot's kernel name. */
+lb_status lb_timing(lb_ctx* ctx, int enable);
+lb_status lb_timing_read(lb_ctx* ctx, int32_t slot, double* total_ms, int64_t* launches);
+int32_t lb_timing_slots(void);
+const char* lb_timing_name(int32_t slot);
+
+/* Bytes of device memory the context holds. */
+lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes);
+
+/* Human-readable text for a status code. */
+const char* lb_strerror(lb_status status);
+
+/* LB_ABI_VERSION of the built library. */
+int32_t lb_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

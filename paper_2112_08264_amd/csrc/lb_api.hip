@@ -1,0 +1,617 @@
+// Host side of liblb's C ABI (include/lb.h): context lifetime, device
+// buffers, argument checks, kernel dispatch on the caller's stream, and
+// per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lb.h"
+#include "lb_kernels.h"
+
+using namespace lbd;
+
+namespace {
+
+enum KernelSlot : int { SLOT_PSI = 0, SLOT_COLLIDE = 1, SLOT_COUNT = 2 };
+const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push"};
+
+constexpr int kTotalsMaxBlocks = 2048;
+
+struct TimedLaunch {
+  int slot;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct lb_ctx {
+  lb_params p{};
+  Geometry g{};
+  StepCoeffs c{};
+  size_t elem = 0;         // bytes per stored population value
+  size_t real_bytes = 0;   // bytes of the arithmetic type
+  size_t grid_bytes = 0;   // bytes of one population grid
+  void* grid[2] = {nullptr, nullptr};
+  int cur = 0;             // grid holding the current state
+  void* psi = nullptr;     // [2][N] pseudopotential, arithmetic type
+  uint8_t* mask = nullptr; // [N], allocated on first use
+  bool has_solid = false;
+  double* partial = nullptr;
+  double* result = nullptr;
+  int* flag = nullptr;
+  double* plane = nullptr;  // [N] float64 staging for host transfers
+  bool has_state = false;
+  hipStream_t stream = nullptr;
+  bool timing = false;
+  std::vector<TimedLaunch> launches;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[SLOT_COUNT] = {0, 0};
+  int64_t t_n[SLOT_COUNT] = {0, 0};
+  int64_t bytes = 0;
+};
+
+namespace {
+
+#define LB_HIP(call)                   \
+  do {                                 \
+    if ((call) != hipSuccess) {        \
+      (void)hipGetLastError();         \
+      return LB_EDEVICE;               \
+    }                                  \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int blocks_for(long long n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+
+lb_status dev_alloc(lb_ctx* ctx, void** ptr, size_t bytes) {
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return LB_ENOMEM;
+  }
+  ctx->bytes += static_cast<int64_t>(bytes);
+  return LB_OK;
+}
+
+void free_all(lb_ctx* ctx) {
+  if (ctx->stream != nullptr || true) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& l : ctx->launches) {
+    (void)hipEventDestroy(l.start);
+    (void)hipEventDestroy(l.stop);
+  }
+  ctx->launches.clear();
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  ctx->event_pool.clear();
+  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi, ctx->mask, ctx->partial, ctx->result, ctx->flag, ctx->plane};
+  for (void* b : bufs)
+    if (b != nullptr) (void)hipFree(b);
+}
+
+hipEvent_t take_event(lb_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Launch through `fn`, bracketing it with events when timing is on.
+template <typename Fn>
+lb_status launch(lb_ctx* ctx, int slot, Fn&& fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx->timing) {
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a == nullptr || b == nullptr) return LB_EDEVICE;
+    LB_HIP(hipEventRecord(a, ctx->stream));
+  }
+  fn();
+  LB_HIP(hipGetLastError());
+  if (ctx->timing) {
+    LB_HIP(hipEventRecord(b, ctx->stream));
+    ctx->launches.push_back({slot, a, b});
+  }
+  return LB_OK;
+}
+
+lb_status fold_timing(lb_ctx* ctx) {
+  if (ctx->launches.empty()) return LB_OK;
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& l : ctx->launches) {
+    float ms = 0.0f;
+    LB_HIP(hipEventElapsedTime(&ms, l.start, l.stop));
+    ctx->t_ms[l.slot] += ms;
+    ctx->t_n[l.slot] += 1;
+    ctx->event_pool.push_back(l.start);
+    ctx->event_pool.push_back(l.stop);
+  }
+  ctx->launches.clear();
+  return LB_OK;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->mask : nullptr; }
+
+// ---------------------------------------------------------------------------
+// Typed implementations
+// ---------------------------------------------------------------------------
+template <int ST>
+lb_status step_impl(lb_ctx* ctx, int n) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  const int nb = blocks_for(ctx->g.N);
+  real* psi = static_cast<real*>(ctx->psi);
+  for (int s = 0; s < n; ++s) {
+    const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+    store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+    lb_status st;
+    if (ctx->has_solid) {
+      st = launch(ctx, SLOT_PSI, [&] {
+        k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(fin, psi, ctx->mask, ctx->g, ctx->c);
+      });
+      if (st != LB_OK) return st;
+      st = launch(ctx, SLOT_COLLIDE, [&] {
+        k_collide_push<ST, true><<<nb, kBlock, 0, ctx->stream>>>(fin, fout, psi, ctx->mask, ctx->g, ctx->c);
+      });
+    } else {
+      st = launch(ctx, SLOT_PSI, [&] {
+        k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(fin, psi, nullptr, ctx->g, ctx->c);
+      });
+      if (st != LB_OK) return st;
+      st = launch(ctx, SLOT_COLLIDE, [&] {
+        k_collide_push<ST, false><<<nb, kBlock, 0, ctx->stream>>>(fin, fout, psi, nullptr, ctx->g, ctx->c);
+      });
+    }
+    if (st != LB_OK) return st;
+    ctx->cur ^= 1;
+  }
+  return LB_OK;
+}
+
+template <int ST>
+lb_status init_impl(lb_ctx* ctx, const double* ra, const double* rb, const double* u) {
+  using store = typename StorageTraits<ST>::store_t;
+  LB_HIP(hipMemsetAsync(ctx->grid[ctx->cur ^ 1], 0, ctx->grid_bytes, ctx->stream));
+  k_init<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ra, rb, u, mask_or_null(ctx),
+                                                               static_cast<store*>(ctx->grid[ctx->cur]), ctx->g, ctx->c);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int ST>
+lb_status decode_impl(lb_ctx* ctx, int plane, double* out) {
+  using store = typename StorageTraits<ST>::store_t;
+  k_decode_plane<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+      static_cast<const store*>(ctx->grid[ctx->cur]), out, mask_or_null(ctx), plane, ctx->g, ctx->c);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int ST>
+lb_status encode_impl(lb_ctx* ctx, int plane, const double* in) {
+  using store = typename StorageTraits<ST>::store_t;
+  k_encode_plane<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+      in, static_cast<store*>(ctx->grid[ctx->cur]), mask_or_null(ctx), plane, ctx->g, ctx->c);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int ST>
+lb_status moments_impl(lb_ctx* ctx, double* ra, double* rb, double* u) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  const store* f = static_cast<const store*>(ctx->grid[ctx->cur]);
+  real* psi = static_cast<real*>(ctx->psi);
+  const int nb = blocks_for(ctx->g.N);
+  if (ctx->has_solid) {
+    k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, ctx->c);
+    k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, ctx->c);
+  } else {
+    k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, ctx->c);
+    k_moments<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, ctx->c);
+  }
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int ST>
+lb_status totals_impl(lb_ctx* ctx, int blocks) {
+  using store = typename StorageTraits<ST>::store_t;
+  k_totals_partial<ST><<<blocks, kBlock, 0, ctx->stream>>>(static_cast<const store*>(ctx->grid[ctx->cur]),
+                                                          mask_or_null(ctx), ctx->g, ctx->c, ctx->partial);
+  LB_HIP(hipGetLastError());
+  k_totals_final<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, blocks, ctx->result);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <typename F>
+lb_status by_storage(const lb_ctx* ctx, F&& f) {
+  switch (ctx->p.storage) {
+    case LB_F64: return f(std::integral_constant<int, ST_F64>{});
+    case LB_F32: return f(std::integral_constant<int, ST_F32>{});
+    case LB_F16_SHIFTED: return f(std::integral_constant<int, ST_F16S>{});
+    default: return LB_EINVAL;
+  }
+}
+
+lb_status ensure_plane(lb_ctx* ctx) {
+  if (ctx->plane != nullptr) return LB_OK;
+  return dev_alloc(ctx, reinterpret_cast<void**>(&ctx->plane), sizeof(double) * static_cast<size_t>(ctx->g.N));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void lb_params_default(lb_params* p) {
+  if (p == nullptr) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 1;
+  p->tau[0] = p->tau[1] = 1.0;
+  p->G = 0.0;
+  p->psi_ref = 1.0;
+  p->rho0[0] = p->rho0[1] = 1.0;
+  p->storage = LB_F64;
+  p->device = 0;
+  p->stream = nullptr;
+}
+
+int32_t lb_abi_version(void) { return LB_ABI_VERSION; }
+
+const char* lb_strerror(lb_status s) {
+  switch (s) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "device allocation failed";
+    case LB_EDEVICE: return "HIP runtime error or no usable device";
+    case LB_ESTATE: return "no state set yet (call lb_set_fields or lb_set_populations first)";
+    case LB_ENONFINITE: return "state holds NaN or Inf";
+  }
+  return "unknown status";
+}
+
+int32_t lb_timing_slots(void) { return SLOT_COUNT; }
+
+const char* lb_timing_name(int32_t slot) {
+  if (slot < 0 || slot >= SLOT_COUNT) return nullptr;
+  return kSlotNames[slot];
+}
+
+lb_status lb_create(const lb_params* params, lb_ctx** out) {
+  if (out == nullptr) return LB_EINVAL;
+  *out = nullptr;
+  if (params == nullptr) return LB_EINVAL;
+  const lb_params& p = *params;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return LB_EINVAL;
+  for (int k = 0; k < 2; ++k) {
+    if (!is_finite(p.tau[k]) || !(p.tau[k] > 0.5)) return LB_EINVAL;
+    if (!is_finite(p.rho0[k])) return LB_EINVAL;
+  }
+  if (!is_finite(p.G) || !is_finite(p.psi_ref) || !(p.psi_ref > 0.0)) return LB_EINVAL;
+  if (p.storage != LB_F64 && p.storage != LB_F32 && p.storage != LB_F16_SHIFTED) return LB_EINVAL;
+  const long long N = static_cast<long long>(p.nx) * p.ny * p.nz;
+  if (N > 0x7fffffffLL - 4096) return LB_EINVAL;  // node index is 32-bit inside the kernels
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) {
+    (void)hipGetLastError();
+    return LB_EDEVICE;
+  }
+  if (p.device < 0 || p.device >= ndev) return LB_EDEVICE;
+  DeviceGuard dg(p.device);
+  if (!dg.ok) return LB_EDEVICE;
+
+  lb_ctx* ctx = new (std::nothrow) lb_ctx();
+  if (ctx == nullptr) return LB_ENOMEM;
+  ctx->p = p;
+  ctx->stream = static_cast<hipStream_t>(p.stream);
+  ctx->g.nx = p.nx;
+  ctx->g.ny = p.ny;
+  ctx->g.nz = p.nz;
+  ctx->g.N = static_cast<int>(N);
+  ctx->g.Npad = (N + 127) / 128 * 128;  // keeps every plane 256-byte aligned
+  ctx->elem = p.storage == LB_F64 ? 8 : (p.storage == LB_F32 ? 4 : 2);
+  ctx->real_bytes = p.storage == LB_F64 ? 8 : 4;
+  ctx->grid_bytes = ctx->elem * static_cast<size_t>(2 * Q) * static_cast<size_t>(ctx->g.Npad);
+
+  StepCoeffs& c = ctx->c;
+  for (int k = 0; k < 2; ++k) {
+    c.om[k] = 1.0 / p.tau[k];
+    c.omc[k] = 1.0 - c.om[k];
+    c.tg[k] = p.tau[k] * p.G;
+    c.omf[k] = static_cast<float>(c.om[k]);
+    c.omcf[k] = static_cast<float>(c.omc[k]);
+    c.tgf[k] = static_cast<float>(c.tg[k]);
+    for (int i = 0; i < Q; ++i)
+      c.shift[k][i] = p.storage == LB_F16_SHIFTED ? static_cast<float>(weight<double>(i) * p.rho0[k]) : 0.0f;
+  }
+  c.G = p.G;
+  c.psi_ref = p.psi_ref;
+  c.Gf = static_cast<float>(p.G);
+  c.psi_reff = static_cast<float>(p.psi_ref);
+
+  lb_status st = LB_OK;
+  for (int b = 0; b < 2 && st == LB_OK; ++b) st = dev_alloc(ctx, &ctx->grid[b], ctx->grid_bytes);
+  if (st == LB_OK) st = dev_alloc(ctx, &ctx->psi, ctx->real_bytes * 2 * static_cast<size_t>(N));
+  if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->partial), sizeof(double) * 8 * kTotalsMaxBlocks);
+  if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->result), sizeof(double) * 8);
+  if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->flag), sizeof(int) * 4);
+  if (st != LB_OK) {
+    free_all(ctx);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return LB_OK;
+}
+
+lb_status lb_destroy(lb_ctx* ctx) {
+  if (ctx == nullptr) return LB_OK;
+  DeviceGuard dg(ctx->p.device);
+  free_all(ctx);
+  delete ctx;
+  return LB_OK;
+}
+
+lb_status lb_set_stream(lb_ctx* ctx, void* stream) {
+  if (ctx == nullptr) return LB_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->p.stream = stream;
+  return LB_OK;
+}
+
+lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes) {
+  if (ctx == nullptr || bytes == nullptr) return LB_EINVAL;
+  *bytes = ctx->bytes;
+  return LB_OK;
+}
+
+lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b, const double* u,
+                        const uint8_t* solid, int on_device) {
+  if (ctx == nullptr || rho_a == nullptr || rho_b == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  const double* dra = rho_a;
+  const double* drb = rho_b;
+  const double* du = u;
+  void* tmp = nullptr;
+  if (!on_device) {
+    const size_t n_in = (u != nullptr ? 5 : 2) * N;
+    if (hipMalloc(&tmp, sizeof(double) * n_in) != hipSuccess) {
+      (void)hipGetLastError();
+      return LB_ENOMEM;
+    }
+    double* t = static_cast<double*>(tmp);
+    bool ok = hipMemcpyAsync(t, rho_a, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess &&
+              hipMemcpyAsync(t + N, rho_b, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (ok && u != nullptr)
+      ok = hipMemcpyAsync(t + 2 * N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      (void)hipFree(tmp);
+      return LB_EDEVICE;
+    }
+    dra = t;
+    drb = t + N;
+    du = u != nullptr ? t + 2 * N : nullptr;
+  }
+  auto release = [&]() {
+    if (tmp != nullptr) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(tmp);
+    }
+  };
+  // validate before touching the state
+  int bad = 0;
+  if (hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream) != hipSuccess) {
+    release();
+    return LB_EDEVICE;
+  }
+  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dra, drb, du, ctx->g.N, ctx->flag);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    release();
+    return LB_EDEVICE;
+  }
+  if (bad) {
+    release();
+    return LB_EINVAL;
+  }
+  if (solid != nullptr) {
+    if (ctx->mask == nullptr) {
+      lb_status st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->mask), N);
+      if (st != LB_OK) {
+        release();
+        return st;
+      }
+    }
+    if (hipMemcpyAsync(ctx->mask, solid, N, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      release();
+      return LB_EDEVICE;
+    }
+    ctx->has_solid = true;
+  } else {
+    ctx->has_solid = false;
+  }
+  lb_status st = by_storage(ctx, [&](auto tag) { return init_impl<decltype(tag)::value>(ctx, dra, drb, du); });
+  if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
+  release();
+  if (st == LB_OK) ctx->has_state = true;
+  return st;
+}
+
+lb_status lb_step(lb_ctx* ctx, int32_t n) {
+  if (ctx == nullptr || n < 0) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  if (n == 0) return LB_OK;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  return by_storage(ctx, [&](auto tag) { return step_impl<decltype(tag)::value>(ctx, n); });
+}
+
+lb_status lb_moments(lb_ctx* ctx, double* rho_a, double* rho_b, double* u, int on_device) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  if (on_device) {
+    lb_status st = by_storage(ctx, [&](auto tag) { return moments_impl<decltype(tag)::value>(ctx, rho_a, rho_b, u); });
+    if (st != LB_OK) return st;
+    LB_HIP(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+  }
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, sizeof(double) * 5 * N) != hipSuccess) {
+    (void)hipGetLastError();
+    return LB_ENOMEM;
+  }
+  double* t = static_cast<double*>(tmp);
+  lb_status st = by_storage(ctx, [&](auto tag) {
+    return moments_impl<decltype(tag)::value>(ctx, rho_a ? t : nullptr, rho_b ? t + N : nullptr, u ? t + 2 * N : nullptr);
+  });
+  bool ok = st == LB_OK;
+  if (ok && rho_a) ok = hipMemcpyAsync(rho_a, t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+  if (ok && rho_b) ok = hipMemcpyAsync(rho_b, t + N, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+  if (ok && u) ok = hipMemcpyAsync(u, t + 2 * N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(ctx->stream) == hipSuccess;
+  (void)hipGetLastError();
+  (void)hipFree(tmp);
+  if (st != LB_OK) return st;
+  return ok ? LB_OK : LB_EDEVICE;
+}
+
+lb_status lb_get_populations(lb_ctx* ctx, double* f, int on_device) {
+  if (ctx == nullptr || f == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  if (!on_device) {
+    lb_status st = ensure_plane(ctx);
+    if (st != LB_OK) return st;
+  }
+  for (int plane = 0; plane < 2 * Q; ++plane) {
+    double* dst = on_device ? f + plane * N : ctx->plane;
+    lb_status st = by_storage(ctx, [&](auto tag) { return decode_impl<decltype(tag)::value>(ctx, plane, dst); });
+    if (st != LB_OK) return st;
+    if (!on_device) {
+      LB_HIP(hipMemcpyAsync(f + plane * N, ctx->plane, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+      LB_HIP(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
+}
+
+lb_status lb_set_populations(lb_ctx* ctx, const double* f, int on_device) {
+  if (ctx == nullptr || f == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  lb_status st = ensure_plane(ctx);
+  if (st != LB_OK) return st;
+  // Reject non-finite input before anything is overwritten.
+  LB_HIP(hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream));
+  for (int plane = 0; plane < 2 * Q; ++plane) {
+    const double* src = f + plane * N;
+    if (!on_device) {
+      LB_HIP(hipMemcpyAsync(ctx->plane, src, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+      src = ctx->plane;
+    }
+    k_check_finite<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(src, ctx->g.N, ctx->flag);
+    LB_HIP(hipGetLastError());
+  }
+  int bad = 0;
+  LB_HIP(hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  if (bad) return LB_EINVAL;
+  if (!ctx->has_state) LB_HIP(hipMemsetAsync(ctx->grid[ctx->cur ^ 1], 0, ctx->grid_bytes, ctx->stream));
+  for (int plane = 0; plane < 2 * Q; ++plane) {
+    const double* src = f + plane * N;
+    if (!on_device) {
+      LB_HIP(hipMemcpyAsync(ctx->plane, src, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream));
+      src = ctx->plane;
+    }
+    st = by_storage(ctx, [&](auto tag) { return encode_impl<decltype(tag)::value>(ctx, plane, src); });
+    if (st != LB_OK) return st;
+  }
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->has_state = true;
+  return LB_OK;
+}
+
+lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite) {
+  if (ctx == nullptr || out == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  int blocks = blocks_for(ctx->g.N);
+  if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
+  lb_status st = by_storage(ctx, [&](auto tag) { return totals_impl<decltype(tag)::value>(ctx, blocks); });
+  if (st != LB_OK) return st;
+  double r[8] = {0};
+  LB_HIP(hipMemcpyAsync(r, ctx->result, sizeof(double) * kTotals, hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  for (int j = 0; j < 5; ++j) out[j] = r[j];
+  const int nf = r[5] != 0.0 ? 1 : 0;
+  if (nonfinite != nullptr) *nonfinite = nf;
+  return nf ? LB_ENONFINITE : LB_OK;
+}
+
+lb_status lb_timing(lb_ctx* ctx, int enable) {
+  if (ctx == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (enable) {
+    lb_status st = fold_timing(ctx);
+    if (st != LB_OK) return st;
+    for (int s = 0; s < SLOT_COUNT; ++s) {
+      ctx->t_ms[s] = 0.0;
+      ctx->t_n[s] = 0;
+    }
+  }
+  ctx->timing = enable != 0;
+  return LB_OK;
+}
+
+lb_status lb_timing_read(lb_ctx* ctx, int32_t slot, double* total_ms, int64_t* launches) {
+  if (ctx == nullptr || slot < 0 || slot >= SLOT_COUNT) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  lb_status st = fold_timing(ctx);
+  if (st != LB_OK) return st;
+  if (total_ms != nullptr) *total_ms = ctx->t_ms[slot];
+  if (launches != nullptr) *launches = ctx->t_n[slot];
+  return LB_OK;
+}
+
+}  // extern "C"

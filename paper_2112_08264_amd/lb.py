@@ -1,0 +1,297 @@
+"""ctypes binding of liblb (include/lb.h): same names, argument marshalling only.
+
+Every step of the lattice-Boltzmann update runs in the HIP kernels of
+liblb.so; this module only converts arguments (NumPy arrays or torch tensors
+to pointers, torch's current stream to a hipStream_t) and turns status codes
+into ``LBError``.  It raises ``LBLibraryMissing`` if the library has not been
+built -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblb.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
+LB_F64, LB_F32, LB_F16_SHIFTED = 0, 1, 2
+STORAGE = {"f64": LB_F64, "f32": LB_F32, "f16s": LB_F16_SHIFTED}
+Q = 19
+
+
+class LBLibraryMissing(RuntimeError):
+    pass
+
+
+class LBError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lb_strerror(status)} (status {status})")
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("tau", ctypes.c_double * 2),
+        ("G", ctypes.c_double),
+        ("psi_ref", ctypes.c_double),
+        ("rho0", ctypes.c_double * 2),
+        ("storage", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol include/lb.h declares
+_P = ctypes.c_void_p
+_SIGNATURES = [
+    ("lb_params_default", None, [ctypes.POINTER(lb_params)]),
+    ("lb_create", ctypes.c_int, [ctypes.POINTER(lb_params), ctypes.POINTER(_P)]),
+    ("lb_destroy", ctypes.c_int, [_P]),
+    ("lb_set_stream", ctypes.c_int, [_P, _P]),
+    ("lb_set_fields", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
+    ("lb_step", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lb_moments", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
+    ("lb_get_populations", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb_set_populations", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb_totals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+    ("lb_timing", ctypes.c_int, [_P, ctypes.c_int]),
+    ("lb_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    ("lb_timing_slots", ctypes.c_int32, []),
+    ("lb_timing_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("lb_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("lb_abi_version", ctypes.c_int32, []),
+]
+SYMBOLS = [s[0] for s in _SIGNATURES]
+
+
+def library():
+    """Load liblb.so once; raise LBLibraryMissing if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LBLibraryMissing(
+                f"{LIB_PATH} is not built; run `python -m paper_2112_08264_amd.build` (hipcc, gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str) -> int:
+    if status != LB_OK:
+        raise LBError(status, where)
+    return status
+
+
+def lb_strerror(status: int) -> str:
+    return library().lb_strerror(int(status)).decode()
+
+
+def lb_abi_version() -> int:
+    return int(library().lb_abi_version())
+
+
+def _current_stream(device: int):
+    try:
+        import torch
+    except ImportError:  # pragma: no cover - torch is part of the image
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(a, dtype_name: str, count: int, what: str):
+    """(pointer, on_device) of a contiguous NumPy array or torch tensor, or (None, 0)."""
+    if a is None:
+        return None, 0
+    mod = type(a).__module__
+    if mod.startswith("torch"):
+        if not a.is_contiguous():
+            raise ValueError(f"{what}: tensor must be contiguous")
+        if str(a.dtype) != f"torch.{dtype_name}":
+            raise TypeError(f"{what}: expected torch.{dtype_name}, got {a.dtype}")
+        if a.numel() != count:
+            raise ValueError(f"{what}: expected {count} elements, got {a.numel()}")
+        return ctypes.c_void_p(a.data_ptr()), int(a.is_cuda)
+    import numpy as np
+    if not isinstance(a, np.ndarray):
+        raise TypeError(f"{what}: expected a NumPy array or a torch tensor")
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{what}: array must be C-contiguous")
+    if a.dtype != np.dtype(dtype_name):
+        raise TypeError(f"{what}: expected {dtype_name}, got {a.dtype}")
+    if a.size != count:
+        raise ValueError(f"{what}: expected {count} elements, got {a.size}")
+    return ctypes.c_void_p(a.ctypes.data), 0
+
+
+def _same_side(*flags):
+    s = {f for f in flags if f is not None}
+    if len(s) > 1:
+        raise ValueError("all arrays of one call must be either host or device")
+    return s.pop() if s else 0
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers, one per C entry point
+# ---------------------------------------------------------------------------
+def lb_params_default() -> lb_params:
+    p = lb_params()
+    library().lb_params_default(ctypes.byref(p))
+    return p
+
+
+def lb_create(params: lb_params) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(library().lb_create(ctypes.byref(params), ctypes.byref(ctx)), "lb_create")
+    return ctx
+
+
+def lb_destroy(ctx) -> None:
+    _check(library().lb_destroy(ctx), "lb_destroy")
+
+
+def lb_set_stream(ctx, stream) -> None:
+    _check(library().lb_set_stream(ctx, stream), "lb_set_stream")
+
+
+def lb_set_fields(ctx, n: int, rho_a, rho_b, u=None, solid=None) -> None:
+    pa, da = _ptr(rho_a, "float64", n, "rho_a")
+    pb, db = _ptr(rho_b, "float64", n, "rho_b")
+    pu, du = _ptr(u, "float64", 3 * n, "u")
+    ps, ds = _ptr(solid, "uint8", n, "solid")
+    on_dev = _same_side(da, db, du if u is not None else None, ds if solid is not None else None)
+    _check(library().lb_set_fields(ctx, pa, pb, pu, ps, on_dev), "lb_set_fields")
+
+
+def lb_step(ctx, nsteps: int) -> None:
+    _check(library().lb_step(ctx, int(nsteps)), "lb_step")
+
+
+def lb_moments(ctx, n: int, rho_a=None, rho_b=None, u=None) -> None:
+    pa, da = _ptr(rho_a, "float64", n, "rho_a")
+    pb, db = _ptr(rho_b, "float64", n, "rho_b")
+    pu, du = _ptr(u, "float64", 3 * n, "u")
+    on_dev = _same_side(da if rho_a is not None else None, db if rho_b is not None else None,
+                        du if u is not None else None)
+    _check(library().lb_moments(ctx, pa, pb, pu, on_dev), "lb_moments")
+
+
+def lb_get_populations(ctx, n: int, f) -> None:
+    pf, df = _ptr(f, "float64", 2 * Q * n, "f")
+    _check(library().lb_get_populations(ctx, pf, df), "lb_get_populations")
+
+
+def lb_set_populations(ctx, n: int, f) -> None:
+    pf, df = _ptr(f, "float64", 2 * Q * n, "f")
+    _check(library().lb_set_populations(ctx, pf, df), "lb_set_populations")
+
+
+def lb_totals(ctx) -> Tuple[Tuple[float, ...], bool]:
+    out = (ctypes.c_double * 5)()
+    nf = ctypes.c_int(0)
+    st = library().lb_totals(ctx, out, ctypes.byref(nf))
+    if st not in (LB_OK, LB_ENONFINITE):
+        _check(st, "lb_totals")
+    return tuple(out), bool(nf.value)
+
+
+def lb_timing(ctx, enable: bool) -> None:
+    _check(library().lb_timing(ctx, int(bool(enable))), "lb_timing")
+
+
+def lb_timing_read(ctx, slot: int) -> Tuple[float, int]:
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(library().lb_timing_read(ctx, int(slot), ctypes.byref(ms), ctypes.byref(n)), "lb_timing_read")
+    return ms.value, n.value
+
+
+def lb_timing_slots() -> int:
+    return int(library().lb_timing_slots())
+
+
+def lb_timing_name(slot: int) -> Optional[str]:
+    r = library().lb_timing_name(int(slot))
+    return r.decode() if r is not None else None
+
+
+def lb_device_bytes(ctx) -> int:
+    b = ctypes.c_int64(0)
+    _check(library().lb_device_bytes(ctx, ctypes.byref(b)), "lb_device_bytes")
+    return b.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience object over one context
+# ---------------------------------------------------------------------------
+class Lattice:
+    """One lattice on one GPU: owns an lb_ctx and forwards to the C entry points.
+
+    ``shape`` is (nz, ny, nx).  Arrays passed in and out are NumPy (host) or
+    torch tensors (host or device), float64, C order [z][y][x].
+    """
+
+    def __init__(self, shape, tau=(1.0, 1.0), G=0.0, psi_ref=1.0, storage="f64", rho0=(1.0, 1.0),
+                 device: int = 0, stream=None):
+        nz, ny, nx = (int(s) for s in shape)
+        p = lb_params_default()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.tau[0], p.tau[1] = float(tau[0]), float(tau[1])
+        p.G = float(G)
+        p.psi_ref = float(psi_ref)
+        p.rho0[0], p.rho0[1] = float(rho0[0]), float(rho0[1])
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.device = int(device)
+        p.stream = stream if stream is not None else _current_stream(device)
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.params = p
+        self.ctx = lb_create(p)
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value is not None:
+            lb_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_fields(self, rho_a, rho_b, u=None, solid=None):
+        lb_set_fields(self.ctx, self.n, rho_a, rho_b, u, solid)
+
+    def step(self, nsteps: int = 1):
+        lb_step(self.ctx, nsteps)
+
+    def moments(self, rho_a=None, rho_b=None, u=None):
+        lb_moments(self.ctx, self.n, rho_a, rho_b, u)
+
+    def get_populations(self, f):
+        lb_get_populations(self.ctx, self.n, f)
+
+    def set_populations(self, f):
+        lb_set_populations(self.ctx, self.n, f)
+
+    def totals(self):
+        return lb_totals(self.ctx)

@@ -1,0 +1,226 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 CPU oracle.
+
+The float64 path is designed to perform the oracle's IEEE operations in the
+oracle's order, so it is held to bit equality on short runs and to the
+1e-12 relative-per-population bar (oracle.population_error) on the 200-step
+32^3 workload.  float32 and float16-shifted storage are held to error bounds
+derived from their precision.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2112_08264_amd as P
+from oracle import lb_oracle as O
+from oracle import naive as N
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-12
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(shape, tau, G, rho_a, rho_b, steps, u=None, solid=None, storage="f64"):
+    """Run ``steps`` steps through the C ABI and return the float64 populations [2][19][z][y][x]."""
+    torch = _torch()
+    n = int(np.prod(shape))
+    with P.Lattice(shape, tau=tau, G=G, storage=storage) as lat:
+        uu = None if u is None else np.ascontiguousarray(np.stack(u).reshape(-1))
+        lat.set_fields(np.ascontiguousarray(rho_a.reshape(-1)), np.ascontiguousarray(rho_b.reshape(-1)), uu,
+                       None if solid is None else np.ascontiguousarray(solid.reshape(-1).astype(np.uint8)))
+        lat.step(steps)
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        torch.cuda.synchronize()
+        return f.cpu().numpy().reshape((2, 19) + tuple(shape))
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 7), (3, 1, 9), (1, 1, 1)])
+def test_f64_bitwise_equal_to_oracle_on_small_and_ragged_boxes(shape):
+    _say(f"case f64 bitwise shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.2, 21)
+    rng = np.random.default_rng(22)
+    u = [rng.uniform(-0.05, 0.05, shape) for _ in range(3)]
+    p = O.Params((0.8, 1.3), 3.5)
+    ref = O.step(O.init_equilibrium(a, b, u), p, n=5)
+    got = run_gpu(shape, p.tau, p.G, a, b, 5, u=u)
+    assert O.population_error(got, ref) <= TOL_F64
+    assert np.array_equal(got, ref), "float64 path is meant to reproduce the oracle bit for bit"
+
+
+def test_f64_mix32_200_steps_within_1e12():
+    w = synth.WORKLOADS["mix32_f64"]
+    _say(f"case {w.name}")
+    a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+    p = O.Params(w.tau, w.G)
+    ref = O.step(O.init_equilibrium(a, b), p, n=w.steps)
+    got = run_gpu(w.shape, w.tau, w.G, a, b, w.steps)
+    err = O.population_error(got, ref)
+    _say(f"  population error {err:.3e}, bit-identical fraction {np.mean(got == ref):.6f}")
+    assert err <= TOL_F64
+    # the run has demixed, so the comparison is not of a near-uniform field
+    assert np.ptp(O.density(ref[0])) > 0.5
+
+
+def test_f64_solids_match_oracle():
+    shape = (12, 14, 16)
+    _say(f"case f64 solids shape={shape}")
+    centres = synth.sphere_centres(shape, 4, 2.5, 31)
+    solid = synth.solid_mask(shape, centres, 2.5)
+    assert 0 < solid.sum() < solid.size
+    a, b = synth.fluid_fields(shape, 0.02, 32)
+    p = O.Params((1.0, 0.9), 3.5)
+    ref = O.step(O.init_equilibrium(a, b, solid=solid), p, solid, n=40)
+    got = run_gpu(shape, p.tau, p.G, a, b, 40, solid=solid)
+    assert O.population_error(got, ref) <= TOL_F64
+    assert np.array_equal(got, ref)
+    assert np.all(got[:, :, solid.astype(bool)] == 0.0)
+
+
+def test_population_roundtrip_and_moments_and_totals():
+    torch = _torch()
+    shape = (6, 7, 8)
+    n = int(np.prod(shape))
+    _say(f"case roundtrip/moments/totals shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.3, 41)
+    f0 = O.step(O.init_equilibrium(a, b), O.Params((0.9, 0.9), 3.5), n=30)
+    p = O.Params((0.9, 0.9), 3.5)
+    with P.Lattice(shape, tau=p.tau, G=p.G) as lat:
+        lat.set_populations(np.ascontiguousarray(f0.reshape(-1)))
+        back = np.empty(2 * 19 * n)
+        lat.get_populations(back)
+        assert np.array_equal(back.reshape(f0.shape), f0)
+        ra, rb, u = np.empty(n), np.empty(n), np.empty(3 * n)
+        lat.moments(ra, rb, u)
+        wa, wb, wu = O.moments(f0, p)
+        np.testing.assert_allclose(ra, wa.ravel(), rtol=1e-15)
+        np.testing.assert_allclose(rb, wb.ravel(), rtol=1e-15)
+        np.testing.assert_allclose(u.reshape(3, -1), np.stack(wu).reshape(3, -1), rtol=1e-13, atol=1e-16)
+        # device-side outputs give the same numbers
+        dra = torch.empty(n, dtype=torch.float64, device="cuda")
+        lat.moments(rho_a=dra)
+        assert np.array_equal(dra.cpu().numpy(), ra)
+        tot, nonfinite = lat.totals()
+        want, wnf = O.totals(f0)
+        assert not nonfinite and not wnf
+        np.testing.assert_allclose(tot[:2], want[:2], rtol=1e-14)
+        np.testing.assert_allclose(tot[2:], want[2:], atol=1e-12)
+        # bitwise repeatable reduction
+        assert lat.totals()[0] == tot
+
+
+def test_conservation_on_gpu_over_many_steps():
+    shape = (24, 24, 24)
+    _say(f"case conservation shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.02, 51)
+    with P.Lattice(shape, tau=(0.8, 0.8), G=3.5) as lat:
+        lat.set_fields(a.ravel().copy(), b.ravel().copy())
+        t0, _ = lat.totals()
+        lat.step(500)
+        t1, nf = lat.totals()
+    assert not nf
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-12
+    assert abs(t1[1] - t0[1]) / t0[1] < 1e-12
+    assert max(abs(v) for v in t1[2:]) / (t0[0] + t0[1]) < 1e-12
+
+
+@pytest.mark.parametrize("storage,tol_rho", [("f32", 1e-4), ("f16s", 2e-3)])
+def test_reduced_storage_error_against_oracle(storage, tol_rho):
+    w = synth.WORKLOADS["mix32_f64"]
+    _say(f"case {storage} vs oracle on {w.name} (100 steps)")
+    a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+    p = O.Params(w.tau, w.G)
+    ref = O.step(O.init_equilibrium(a, b), p, n=100)
+    got = run_gpu(w.shape, w.tau, w.G, a, b, 100, storage=storage)
+    drho = max(np.max(np.abs(O.density(got[k]) - O.density(ref[k]))) for k in range(2))
+    _say(f"  max |drho| = {drho:.3e}")
+    assert drho <= tol_rho
+
+
+def test_error_paths_on_device():
+    torch = _torch()
+    shape = (4, 4, 4)
+    n = 64
+    with P.Lattice(shape, tau=(1.0, 1.0), G=3.5) as lat:
+        with pytest.raises(P.LBError) as e:
+            lat.step(1)
+        assert e.value.status == P.LB_ESTATE
+        with pytest.raises(P.LBError) as e:
+            P.lb_moments(lat.ctx, n, np.empty(n))
+        assert e.value.status == P.LB_ESTATE
+        bad = np.ones(n)
+        bad[5] = np.nan
+        with pytest.raises(P.LBError) as e:
+            lat.set_fields(bad, np.ones(n))
+        assert e.value.status == P.LB_EINVAL
+        neg = np.ones(n)
+        neg[3] = -0.5
+        with pytest.raises(P.LBError) as e:
+            lat.set_fields(np.ones(n), neg)
+        assert e.value.status == P.LB_EINVAL
+        fbad = np.ones(2 * 19 * n)
+        fbad[100] = np.inf
+        with pytest.raises(P.LBError) as e:
+            lat.set_populations(fbad)
+        assert e.value.status == P.LB_EINVAL
+        with pytest.raises(P.LBError) as e:
+            lat.step(-1)
+        assert e.value.status == P.LB_EINVAL
+        # a finite state whose momentum is absurd overflows within a step
+        # (the velocity squared exceeds the float64 range); totals flag it
+        fa = np.ones((2, 19, n))
+        fa[0, 1] = 1e200
+        fa[0, 2] = -1e200
+        lat.set_populations(fa.ravel())
+        lat.step(2)
+        _, nonfinite = lat.totals()
+        assert nonfinite
+        # recovers after a valid reset
+        lat.set_fields(np.ones(n), np.ones(n))
+        lat.step(1)
+        assert not lat.totals()[1]
+
+
+@pytest.mark.slow
+def test_full_size_spinodal256_sampled_one_step_parity():
+    """At the benchmark size: run on the GPU, then check one more GPU step at
+    sampled nodes against the per-node oracle twin computed from the GPU state."""
+    torch = _torch()
+    w = synth.WORKLOADS["spinodal256_f64"]
+    shape = w.shape
+    n = w.nodes
+    _say(f"case {w.name} sampled one-step parity")
+    a, b = synth.fluid_fields(shape, w.amp, w.seed)
+    with P.Lattice(shape, tau=w.tau, G=w.G) as lat:
+        lat.set_fields(a.ravel().copy(), b.ravel().copy())
+        t0, _ = lat.totals()
+        lat.step(50)
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        f_host = f.cpu().numpy().reshape((2, 19) + shape)
+        lat.step(1)
+        lat.get_populations(f)
+        t1, nf = lat.totals()
+    assert not nf
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-12 and abs(t1[1] - t0[1]) / t0[1] < 1e-12
+    f1 = f.view(2, 19, *shape)
+    sites = synth.sample_sites(shape, 24, 61)
+    want = N.step_at(f_host, sites, w.tau, w.G)
+    for s, (x, y, z) in enumerate(sites):
+        got = f1[:, :, z, y, x].cpu().numpy()
+        err = np.max(np.abs(got - want[s]) / np.maximum(np.abs(want[s]), 1e-3 * O.W[None, :]))
+        assert err <= 1e-13, (x, y, z, err)
