@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "GLUPS & % HBM roofline, 2-comp D3Q19 256^3; adjoint/forward time ratio"
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2}
 KERNEL_SOURCES = ["paper_2112_08264_amd/csrc/lb_device.h", "paper_2112_08264_amd/csrc/lb_kernels.h",
+                  "paper_2112_08264_amd/csrc/lb_fused.h",
                   "paper_2112_08264_amd/csrc/lb_api.hip"]
 
 
@@ -48,10 +49,10 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, timing_slots=True):
+def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel="auto", timing_slots=True):
     """Run one storage form; return a dict of timings."""
     a, b = fields
-    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0)
+    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0, kernel=kernel)
     try:
         lat.set_fields(a, b)
         lat.step(warmup)
@@ -80,6 +81,25 @@ def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, timing
     mass_drift = max(abs(tot1[k] - tot0[k]) / abs(tot0[k]) for k in range(2))
     return {"event_ms": ev_ms, "wall_ms": (w1 - w0) * 1e3, "kernels": kernels, "nonfinite": nonfinite,
             "mass_drift": mass_drift}
+
+
+def copy_calibration(torch, nbytes: int = 2 << 30, reps: int = 5):
+    """Plain device-to-device copy of a known size: the reference kernel for
+    scaling rocprofv3's FETCH_SIZE / WRITE_SIZE and for attainable bandwidth."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(w, fields_fn):
@@ -136,6 +156,9 @@ def main(argv=None) -> int:
     ap.add_argument("--form-steps", type=int, default=200, help="timed steps of the float32 / float16 forms")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass"])
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -153,13 +176,16 @@ def main(argv=None) -> int:
         return 1
     P.library()  # raises if liblb.so is missing: there is no fallback
     torch.cuda.set_device(0)
+    if args.calibrate:
+        print(json.dumps(copy_calibration(torch)), flush=True)
+        return 0
     w = synth.WORKLOADS[args.workload]
     log(f"bench: workload {w.name} {w.shape} storage {w.storage}; generating inputs")
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
     fields = (a.reshape(-1), b.reshape(-1))
 
     log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
-    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields)
+    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields, kernel=args.kernel)
     ms_step = main_run["event_ms"] / args.steps
     glups = w.nodes / (ms_step * 1e-3) / 1e9
     bpl = algorithmic_bytes_per_lup(w.storage)
@@ -181,7 +207,7 @@ def main(argv=None) -> int:
             if st == w.storage:
                 continue
             log(f"bench: form {st}, {args.form_steps} steps")
-            r = time_form(P, torch, w, st, args.form_steps, 10, fields)
+            r = time_form(P, torch, w, st, args.form_steps, 10, fields, kernel=args.kernel)
             ms = r["event_ms"] / args.form_steps
             g = w.nodes / (ms * 1e-3) / 1e9
             forms[st] = {"glups": round(g, 4), "ms_per_step": round(ms, 4),
@@ -218,6 +244,7 @@ def main(argv=None) -> int:
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),
+        "kernel": args.kernel,
         "kernel_source_digest": source_digest(),
     }
     print(json.dumps(out), flush=True)

@@ -143,6 +143,15 @@ lb_status lb_timing_read(lb_ctx* ctx, int32_t slot, double* total_ms, int64_t* l
 int32_t lb_timing_slots(void);
 const char* lb_timing_name(int32_t slot);
 
+/* Step implementation.  LB_KERNEL_FUSED (the default; LB_KERNEL_AUTO picks
+ * it) reads and writes every population once per step: one kernel marches
+ * z-columns and keeps the pseudopotential of three planes in LDS.
+ * LB_KERNEL_TWO_PASS computes the pseudopotential field in a first kernel
+ * and collides and streams in a second.  Both give bitwise identical results
+ * for LB_F64.  Errors: LB_EINVAL (unknown value). */
+typedef enum { LB_KERNEL_AUTO = 0, LB_KERNEL_FUSED = 1, LB_KERNEL_TWO_PASS = 2 } lb_kernel;
+lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel);
+
 /* Bytes of device memory the context holds. */
 lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes);
 

@@ -10,14 +10,16 @@
 #include <vector>
 
 #include "lb.h"
+#include "lb_fused.h"
 #include "lb_kernels.h"
 
 using namespace lbd;
 
 namespace {
 
-enum KernelSlot : int { SLOT_PSI = 0, SLOT_COLLIDE = 1, SLOT_COUNT = 2 };
-const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push"};
+enum KernelSlot : int { SLOT_PSI = 0, SLOT_COLLIDE = 1, SLOT_FUSED = 2, SLOT_COUNT = 3 };
+const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused"};
+constexpr int kFusedTY = 8;
 
 constexpr int kTotalsMaxBlocks = 2048;
 
@@ -49,8 +51,10 @@ struct lb_ctx {
   bool timing = false;
   std::vector<TimedLaunch> launches;
   std::vector<hipEvent_t> event_pool;
-  double t_ms[SLOT_COUNT] = {0, 0};
-  int64_t t_n[SLOT_COUNT] = {0, 0};
+  double t_ms[SLOT_COUNT] = {0, 0, 0};
+  int64_t t_n[SLOT_COUNT] = {0, 0, 0};
+  int kernel = LB_KERNEL_FUSED;
+  FusedTiling tiling{};
   int64_t bytes = 0;
 };
 
@@ -158,7 +162,40 @@ const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->ma
 // Typed implementations
 // ---------------------------------------------------------------------------
 template <int ST>
+lb_status fused_step_impl(lb_ctx* ctx, int n) {
+  using store = typename StorageTraits<ST>::store_t;
+  const FusedTiling t = ctx->tiling;
+  for (int s = 0; s < n; ++s) {
+    const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+    store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+    // float64: component-pair waves without register prefetch (two planes of
+    // float64 populations fill the register budget); float32 arithmetic:
+    // single-component waves with a prefetch depth of three planes.
+    lb_status st = launch(ctx, SLOT_FUSED, [&] {
+      if constexpr (ST == ST_F64) {
+        if (ctx->has_solid)
+          k_fused_pair<ST, true, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, ctx->mask, ctx->g, ctx->c, t);
+        else
+          k_fused_pair<ST, false, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t);
+      } else {
+        if (ctx->has_solid)
+          k_fused<ST, true, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, ctx->mask, ctx->g, ctx->c, t);
+        else
+          k_fused<ST, false, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t);
+      }
+    });
+    if (st != LB_OK) return st;
+    ctx->cur ^= 1;
+  }
+  return LB_OK;
+}
+
+// The fused kernel addresses a population plane with 32-bit byte offsets.
+bool fused_fits(const lb_ctx* ctx) { return static_cast<double>(ctx->g.N) * ctx->elem < 4294967296.0; }
+
+template <int ST>
 lb_status step_impl(lb_ctx* ctx, int n) {
+  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) return fused_step_impl<ST>(ctx, n);
   using store = typename StorageTraits<ST>::store_t;
   using real = typename StorageTraits<ST>::real;
   const int nb = blocks_for(ctx->g.N);
@@ -353,6 +390,32 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
   }
   c.G = p.G;
   c.psi_ref = p.psi_ref;
+
+  // Fused-kernel tiling: 32 x kFusedTY columns, z split into chunks so that
+  // there are about four workgroups per compute unit.
+  FusedTiling& t = ctx->tiling;
+  t.tiles_x = (p.nx + kFusedTX - 1) / kFusedTX;
+  t.tiles_y = (p.ny + kFusedTY - 1) / kFusedTY;
+  {
+    const long long cols = static_cast<long long>(t.tiles_x) * t.tiles_y;
+    // float64 runs one workgroup per compute unit, float32 arithmetic two;
+    // two rounds of workgroups over the 256 compute units balance chunk
+    // overhead (one extra plane read per chunk end) against tail effects.
+    const long long target = p.storage == LB_F64 ? 1024 : 512;
+    long long want = (target + cols - 1) / cols;  // chunks wanted
+    if (want < 1) want = 1;
+    int chunk = static_cast<int>((p.nz + want - 1) / want);
+    if (chunk < 4) chunk = 4;
+    if (chunk > p.nz) chunk = p.nz;
+    t.chunk = chunk;
+    t.chunks = (p.nz + chunk - 1) / chunk;
+    const long long total = cols * t.chunks;
+    if (total > 0x7fffffffLL) {
+      delete ctx;
+      return LB_EINVAL;
+    }
+    t.total = static_cast<int>(total);
+  }
   c.Gf = static_cast<float>(p.G);
   c.psi_reff = static_cast<float>(p.psi_ref);
 
@@ -383,6 +446,14 @@ lb_status lb_set_stream(lb_ctx* ctx, void* stream) {
   if (ctx == nullptr) return LB_EINVAL;
   ctx->stream = static_cast<hipStream_t>(stream);
   ctx->p.stream = stream;
+  return LB_OK;
+}
+
+lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (kernel == LB_KERNEL_AUTO) kernel = LB_KERNEL_FUSED;
+  if (kernel != LB_KERNEL_FUSED && kernel != LB_KERNEL_TWO_PASS) return LB_EINVAL;
+  ctx->kernel = kernel;
   return LB_OK;
 }
 

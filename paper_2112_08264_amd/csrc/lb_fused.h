@@ -1,0 +1,416 @@
+// Single-pass step: one HBM read and one HBM write of every population.
+//
+// The Shan-Chen force at x needs psi of the *same* time level at the 18
+// neighbours of x, and psi there needs those neighbours' populations.  A
+// workgroup therefore owns a column of TX x TY nodes and marches through a
+// chunk of z-planes, keeping psi of four consecutive planes of its tile plus
+// a one-node halo ring in an LDS ring buffer.  The tile's own populations
+// are read from HBM once and stay in registers until their plane is
+// collided; the halo's populations belong to neighbouring columns that are
+// marched at the same time, so re-reading them mostly hits the caches.  Each
+// chunk also reads the plane before and the plane after it.
+//
+// Software pipeline of depth D >= 2 (one barrier per plane): iteration z
+// issues the loads of plane z + D, collides plane z (psi of z - 1, z, z + 1
+// are already in LDS) and pushes its post-collision populations, then turns
+// the plane z + D loads into psi.  The loads are in flight during D
+// collisions' worth of work, and since they are issued before that plane's
+// stores, waiting for them never waits for the stores.  Interior populations
+// of planes z .. z + D - 1 stay in registers.
+//
+// Lane layout: TX = 32.  Each wave carries one component for two rows of the
+// tile (lanes 0..31 row 2r, lanes 32..63 row 2r + 1), so every population
+// plane it touches has a wave-uniform base address.  The other component's
+// density and momentum at the same node, needed for the common velocity,
+// come from an LDS exchange written one iteration ahead.
+//
+// Streaming is push: f*_i(x) goes to x + c_i in the other grid, or back into
+// (x, opp(i)) when x + c_i is solid.  Both grids hold pre-collision
+// populations in the library's structure-of-arrays layout.
+//
+// Workgroups are numbered so that the ones the hardware sends to the same
+// XCD (workgroup id modulo 8) take a contiguous run of tiles of one z-chunk:
+// neighbouring columns then share that XCD's L2 for their halo reads.
+#pragma once
+
+#include "lb_kernels.h"
+
+namespace lbd {
+
+constexpr int kFusedTX = 32;
+constexpr int kXCDs = 8;
+
+struct FusedTiling {
+  int tiles_x, tiles_y;  // tile counts along x and y
+  int chunk;             // planes per z-chunk
+  int chunks;            // number of z-chunks
+  int total;             // tiles_x * tiles_y * chunks
+};
+
+// Workgroup id -> work item, XCD-contiguous (see above).
+__device__ __forceinline__ int fused_work_item(int b, int total) {
+  const int q = total / kXCDs, r = total % kXCDs;
+  const int j = b % kXCDs, s = b / kXCDs;
+  return j * q + (j < r ? j : r) + s;
+}
+
+template <int ST, bool SOLID, int TY, int D>
+__global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
+                                                   const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c,
+                                                   FusedTiling t) {
+  using real = real_t<ST>;
+  using store = store_t<ST>;
+  constexpr int TX = kFusedTX;
+  constexpr int RX = TX + 2, RY = TY + 2;  // ring plane incl. halo
+  constexpr int NS = D + 2;                // ring slots: planes z - 1 .. z + D
+  constexpr int NX = D + 1;                // exchange slots: planes z .. z + D
+  static_assert(D >= 2, "psi of plane z + 1 must be ready before plane z is collided");
+  static_assert(TY % 2 == 0 && TY >= 6, "three row-pairs per component carry the halo");
+  __shared__ real ring[NS][2][RY][RX];
+  __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
+  __shared__ uint8_t ring_solid[SOLID ? NS : 1][SOLID ? RY : 1][SOLID ? RX : 1];
+
+  const int w = fused_work_item(blockIdx.x, t.total);
+  const int chunk = w / (t.tiles_x * t.tiles_y);
+  const int tile = w - chunk * (t.tiles_x * t.tiles_y);
+  const int ty0 = (tile / t.tiles_x) * TY, tx0 = (tile % t.tiles_x) * TX;
+  const int z0 = chunk * t.chunk;
+  const int zlen = min(t.chunk, g.nz - z0);
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = __builtin_amdgcn_readfirstlane(wave & 1);    // component of this wave
+  const int rp = __builtin_amdgcn_readfirstlane(wave >> 1);  // row pair
+  const int lx = lane & 31, ly = 2 * rp + (lane >> 5);
+  // interior node of this lane, wrapped into the box (lanes past the box edge
+  // read the wrapped node so that every ring slot holds the right psi)
+  const int gx = (tx0 + lx) % g.nx, gy = (ty0 + ly) % g.ny;
+  const bool active = (tx0 + lx) < g.nx && (ty0 + ly) < g.ny;
+  const uint32_t row = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy;
+  const uint32_t plane_n = (uint32_t)g.nx * (uint32_t)g.ny;
+
+  // halo node of this lane: row pair 0 -> row above, 1 -> row below,
+  // 2 -> left and right columns, others none
+  bool has_halo = false;
+  int hx = 0, hy = 0;
+  if (rp == 0 && lane < RX) { has_halo = true; hx = lane - 1; hy = -1; }
+  if (rp == 1 && lane < RX) { has_halo = true; hx = lane - 1; hy = TY; }
+  if (rp == 2 && lane < 2 * TY) { has_halo = true; hx = lane < TY ? -1 : TX; hy = lane < TY ? lane : lane - TY; }
+  const int hgx = ((tx0 + hx) % g.nx + g.nx) % g.nx;
+  const int hgy = ((ty0 + hy) % g.ny + g.ny) % g.ny;
+  const uint32_t hrow = (uint32_t)hgx + (uint32_t)g.nx * (uint32_t)hgy;
+
+  // Plane bases are wave-uniform (scalar registers); per-lane offsets are
+  // 32-bit byte offsets (the host only selects this kernel when
+  // N * sizeof(store) < 2^32).
+  const char* __restrict__ fk = reinterpret_cast<const char*>(fin + (size_t)(k * Q) * (size_t)g.Npad);
+  char* __restrict__ ok = reinterpret_cast<char*>(fout + (size_t)(k * Q) * (size_t)g.Npad);
+  const size_t pbytes = (size_t)g.Npad * sizeof(store);
+  constexpr uint32_t ES = sizeof(store);
+
+  auto wrapz = [&](int z) { return z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z); };
+  auto slot = [&](int z) { return (z - z0 + 1 + NS) % NS; };  // ring slot of plane z (z0-1 .. z0+zlen)
+  auto xslot = [&](int z) { return (z - z0 + 1 + NX) % NX; };  // exchange slot of plane z
+  // The iteration that collides plane z (reading psi of z - 1 .. z + 1 and the
+  // exchange of z) writes plane z + D; with D + 2 ring slots and D + 1
+  // exchange slots no write lands where another wave may still be reading.
+
+  auto load19 = [&](uint32_t n, real (&v)[Q]) {
+    const uint32_t b = n * ES;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      v[i] = decode<ST>(*reinterpret_cast<const store*>(fk + (size_t)i * pbytes + b), c.shift[k][i]);
+  };
+  auto psi_from = [&](const real (&v)[Q], bool solid) -> real {
+    if (SOLID && solid) return real(0);
+    return pseudopotential(density<real>(v), coef_ref<real>(c));
+  };
+  // psi of plane z from loaded values -> ring; interior density and momentum -> exchange
+  auto publish = [&](int z, const real (&v)[Q], const real (&h)[Q]) {
+    const int s = slot(z), par = xslot(z);
+    bool solid = false, hsolid = false;
+    if constexpr (SOLID) {
+      solid = mask[row + plane_n * (uint32_t)wrapz(z)] != 0;
+      if (has_halo) hsolid = mask[hrow + plane_n * (uint32_t)wrapz(z)] != 0;
+    }
+    const real rho = density<real>(v);
+    ring[s][k][ly + 1][lx + 1] = (SOLID && solid) ? real(0) : pseudopotential(rho, coef_ref<real>(c));
+    xch[par][k][0][ly][lx] = rho;
+    xch[par][k][1][ly][lx] = lattice_sum<0, 0, real>(v);
+    xch[par][k][2][ly][lx] = lattice_sum<1, 0, real>(v);
+    xch[par][k][3][ly][lx] = lattice_sum<2, 0, real>(v);
+    if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid;
+    if (has_halo) {
+      ring[s][k][hy + 1][hx + 1] = psi_from(h, hsolid);
+      if constexpr (SOLID) if (k == 0) ring_solid[s][hy + 1][hx + 1] = hsolid;
+    }
+  };
+
+  real hold[D][Q], pre[Q], hpre[Q];  // hold[d]: populations of plane z + d
+  // prologue: psi of planes z0 - 1 .. z0 + D - 1, populations of z0 .. z0 + D - 1
+  {
+    const uint32_t zo = plane_n * (uint32_t)wrapz(z0 - 1);
+    load19(row + zo, pre);
+    if (has_halo) load19(hrow + zo, hpre);
+    publish(z0 - 1, pre, hpre);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const uint32_t zo = plane_n * (uint32_t)wrapz(z0 + d);
+    load19(row + zo, hold[d]);
+    if (has_halo) load19(hrow + zo, hpre);
+    publish(z0 + d, hold[d], hpre);
+  }
+  __syncthreads();
+
+  const real omk = coef_om<real>(c, k), omck = coef_omc<real>(c, k), tgk = coef_tg<real>(c, k);
+  const real omA = coef_om<real>(c, 0), omB = coef_om<real>(c, 1);
+  const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx == g.nx - 1 ? 0 : gx + 1;
+  const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
+  const uint32_t X[3] = {(uint32_t)xm, (uint32_t)gx, (uint32_t)xp};
+  const uint32_t Y[3] = {(uint32_t)g.nx * ym, (uint32_t)g.nx * gy, (uint32_t)g.nx * yp};
+
+  for (int j = 0; j < zlen; ++j) {
+    const int z = z0 + j;
+    const bool more = j + D <= zlen;  // psi of plane z + D is needed by a later collision
+    // ---- A: issue the loads of plane z + D ----
+    if (more) {
+      const uint32_t zo = plane_n * (uint32_t)wrapz(z + D);
+      load19(row + zo, pre);
+      if (has_halo) load19(hrow + zo, hpre);
+    }
+    __asm__ volatile("" ::: "memory");
+
+    // ---- B: collide plane z ----
+    const int sm = slot(z - 1), s0 = slot(z), sp = slot(z + 1);
+    const int par = xslot(z);
+    bool here_solid = false;
+    if constexpr (SOLID) here_solid = ring_solid[s0][ly + 1][lx + 1] != 0;
+    const real rhoA = xch[par][0][0][ly][lx], rhoB = xch[par][1][0][ly][lx];
+    const real rho_k = k == 0 ? rhoA : rhoB;
+    const real den = omA * rhoA + omB * rhoB;
+    real up[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) up[a] = (omA * xch[par][0][1 + a][ly][lx] + omB * xch[par][1][1 + a][ly][lx]) / den;
+    real S[3] = {real(0), real(0), real(0)};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+      const real tt = weight<real>(i) * ring[si][1 - k][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      if (CX[i] == 1) S[0] = S[0] + tt;
+      if (CX[i] == -1) S[0] = S[0] - tt;
+      if (CY[i] == 1) S[1] = S[1] + tt;
+      if (CY[i] == -1) S[1] = S[1] - tt;
+      if (CZ[i] == 1) S[2] = S[2] + tt;
+      if (CZ[i] == -1) S[2] = S[2] - tt;
+    }
+    const real psi_k = ring[s0][k][ly + 1][lx + 1];
+    const real ratio = rho_k == real(0) ? real(1) : psi_k / rho_k;
+    const real ak = tgk * ratio;
+    const real vx = up[0] - ak * S[0];
+    const real vy = up[1] - ak * S[1];
+    const real vz = up[2] - ak * S[2];
+    const real vv = (vx * vx + vy * vy) + vz * vz;
+    const real t15 = real(1.5) * vv;
+    if (active && !here_solid) {
+      const uint32_t Z[3] = {plane_n * (uint32_t)wrapz(z - 1), plane_n * (uint32_t)z, plane_n * (uint32_t)wrapz(z + 1)};
+      const uint32_t here = row + Z[1];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real cu = cdot<real>(i, vx, vy, vz);
+        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+        const real fs = omck * hold[0][i] + omk * feq;
+        uint32_t dn = X[CX[i] + 1] + Y[CY[i] + 1] + Z[CZ[i] + 1];
+        int di = i;
+        if constexpr (SOLID) {
+          if (i != 0) {
+            const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+            if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) {
+              dn = here;
+              di = OPP[i];
+            }
+          }
+        }
+        *reinterpret_cast<store*>(ok + (size_t)di * pbytes + dn * ES) = encode<ST>(fs, c.shift[k][i]);
+      }
+    }
+
+    // ---- C: psi and exchange of plane z + D ----
+    if (more) publish(z + D, pre, hpre);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+#pragma unroll
+      for (int d = 0; d + 1 < D; ++d) hold[d][i] = hold[d + 1][i];
+      hold[D - 1][i] = pre[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Component-pair variant (used for float64).  Each wave holds one row of
+// TX = 32 nodes for both components: lanes 0..31 carry component A, lanes
+// 32..63 component B of the same nodes, and the partner lane (lane ^ 32)
+// supplies the other component's density and momentum by a lane shuffle.
+// No register prefetch: the plane z + 1 loads are consumed in the same
+// iteration, which keeps the float64 register budget (two planes of 19
+// populations) within 256 VGPRs without spilling.  Ring of three planes.
+// ---------------------------------------------------------------------------
+template <int ST, bool SOLID, int TY>
+__global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
+                                                        store_t<ST>* __restrict__ fout,
+                                                        const uint8_t* __restrict__ mask, Geometry g,
+                                                        StepCoeffs c, FusedTiling t) {
+  using real = real_t<ST>;
+  constexpr int TX = kFusedTX;
+  constexpr int RX = TX + 2, RY = TY + 2;
+  static_assert(2 * (2 * RX + 2 * TY) <= 64 * TY, "too few lanes for the halo tasks");
+  __shared__ real ring[3][2][RY][RX];
+  __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
+
+  const int w = fused_work_item(blockIdx.x, t.total);
+  const int chunk = w / (t.tiles_x * t.tiles_y);
+  const int tile = w - chunk * (t.tiles_x * t.tiles_y);
+  const int ty0 = (tile / t.tiles_x) * TY, tx0 = (tile % t.tiles_x) * TX;
+  const int z0 = chunk * t.chunk;
+  const int zlen = min(t.chunk, g.nz - z0);
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = lane >> 5;
+  const int lx = lane & 31, ly = wave;
+  const int gx = (tx0 + lx) % g.nx, gy = (ty0 + ly) % g.ny;
+  const bool active = (tx0 + lx) < g.nx && (ty0 + ly) < g.ny;
+  const long long row = (long long)gx + (long long)g.nx * gy;
+  const long long plane_n = (long long)g.nx * g.ny;
+  const long long kplane = (long long)(k * Q) * g.Npad;
+
+  // halo task of this lane, if any: node h of the ring's border, component hk
+  const int nh = 2 * RX + 2 * TY;
+  const int task = threadIdx.x;
+  const bool has_halo = task < 2 * nh;
+  int hx = 0, hy = 0, hk = 0;
+  if (has_halo) {
+    const int h = task >> 1;
+    hk = task & 1;
+    if (h < RX) { hx = h - 1; hy = -1; }
+    else if (h < 2 * RX) { hx = h - RX - 1; hy = TY; }
+    else if (h < 2 * RX + TY) { hx = -1; hy = h - 2 * RX; }
+    else { hx = TX; hy = h - 2 * RX - TY; }
+  }
+  const int hgx = ((tx0 + hx) % g.nx + g.nx) % g.nx;
+  const int hgy = ((ty0 + hy) % g.ny + g.ny) % g.ny;
+  const long long hrow = (long long)hgx + (long long)g.nx * hgy;
+  const long long hkplane = (long long)(hk * Q) * g.Npad;
+
+  auto wrapz = [&](int z) { return z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z); };
+
+  auto psi_of = [&](long long n, long long kp, int kk, bool solid, real (&v)[Q]) -> real {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = decode<ST>(fin[kp + (long long)i * g.Npad + n], c.shift[kk][i]);
+    if (SOLID && solid) return real(0);
+    return pseudopotential(density<real>(v), coef_ref<real>(c));
+  };
+
+  // ring slot s <- psi of plane z; interior lanes keep their populations in `keep`
+  auto fill = [&](int s, int z, real (&keep)[Q]) {
+    const long long zoff = plane_n * z;
+    {
+      const long long n = row + zoff;
+      bool solid = false;
+      if constexpr (SOLID) solid = mask[n] != 0;
+      const real p = psi_of(n, kplane, k, solid, keep);
+      ring[s][k][ly + 1][lx + 1] = p;
+      if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid;
+    }
+    if (has_halo) {
+      const long long n = hrow + zoff;
+      bool solid = false;
+      if constexpr (SOLID) solid = mask[n] != 0;
+      real tmp[Q];
+      const real p = psi_of(n, hkplane, hk, solid, tmp);
+      ring[s][hk][hy + 1][hx + 1] = p;
+      if constexpr (SOLID) if (hk == 0) ring_solid[s][hy + 1][hx + 1] = solid;
+    }
+  };
+
+  real cur[Q], nxt[Q];
+  fill(0, wrapz(z0 - 1), nxt);  // populations of plane z0 - 1 are not needed
+  fill(1, z0, cur);
+  __syncthreads();
+
+  const real omk = coef_om<real>(c, k), omck = coef_omc<real>(c, k), tgk = coef_tg<real>(c, k);
+  const real omA = coef_om<real>(c, 0), omB = coef_om<real>(c, 1);
+
+  for (int j = 0; j < zlen; ++j) {
+    const int z = z0 + j;
+    const int sm = j % 3, s0 = (j + 1) % 3, sp = (j + 2) % 3;  // ring slots of planes z-1, z, z+1
+    fill(sp, wrapz(z + 1), nxt);
+    __syncthreads();
+
+    bool here_solid = false;
+    if constexpr (SOLID) here_solid = ring_solid[s0][ly + 1][lx + 1] != 0;
+    const real rho_k = density<real>(cur);
+    real m_k[3] = {lattice_sum<0, 0, real>(cur), lattice_sum<1, 0, real>(cur), lattice_sum<2, 0, real>(cur)};
+    const real rho_o = __shfl_xor(rho_k, 32, 64);
+    real m_o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m_o[a] = __shfl_xor(m_k[a], 32, 64);
+    const real rhoA = k == 0 ? rho_k : rho_o, rhoB = k == 0 ? rho_o : rho_k;
+    const real den = omA * rhoA + omB * rhoB;
+    real up[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const real mA = k == 0 ? m_k[a] : m_o[a], mB = k == 0 ? m_o[a] : m_k[a];
+      up[a] = (omA * mA + omB * mB) / den;
+    }
+    real S[3] = {real(0), real(0), real(0)};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+      const real tt = weight<real>(i) * ring[si][1 - k][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      if (CX[i] == 1) S[0] = S[0] + tt;
+      if (CX[i] == -1) S[0] = S[0] - tt;
+      if (CY[i] == 1) S[1] = S[1] + tt;
+      if (CY[i] == -1) S[1] = S[1] - tt;
+      if (CZ[i] == 1) S[2] = S[2] + tt;
+      if (CZ[i] == -1) S[2] = S[2] - tt;
+    }
+    const real psi_k = ring[s0][k][ly + 1][lx + 1];
+    const real ratio = rho_k == real(0) ? real(1) : psi_k / rho_k;
+    const real ak = tgk * ratio;
+    const real vx = up[0] - ak * S[0];
+    const real vy = up[1] - ak * S[1];
+    const real vz = up[2] - ak * S[2];
+    const real vv = (vx * vx + vy * vy) + vz * vz;
+    const real t15 = real(1.5) * vv;
+
+    if (active && !here_solid) {
+      const int zm = wrapz(z - 1), zp = wrapz(z + 1);
+      const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx == g.nx - 1 ? 0 : gx + 1;
+      const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
+      const int X[3] = {xm, gx, xp};
+      const int Y[3] = {ym, gy, yp};
+      const int Z[3] = {zm, z, zp};
+      const long long here = row + plane_n * z;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real cu = cdot<real>(i, vx, vy, vz);
+        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+        const real fs = omck * cur[i] + omk * feq;
+        long long dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
+                        (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
+        if constexpr (SOLID) {
+          if (i != 0) {
+            const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+            if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) dst = kplane + (long long)OPP[i] * g.Npad + here;
+          }
+        }
+        fout[dst] = encode<ST>(fs, c.shift[k][i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    __syncthreads();
+  }
+}
+
+}  // namespace lbd

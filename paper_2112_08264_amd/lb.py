@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "liblb.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
 LB_F64, LB_F32, LB_F16_SHIFTED = 0, 1, 2
+LB_KERNEL_AUTO, LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1, 2
+KERNELS = {"auto": LB_KERNEL_AUTO, "fused": LB_KERNEL_FUSED, "two_pass": LB_KERNEL_TWO_PASS}
 STORAGE = {"f64": LB_F64, "f32": LB_F32, "f16s": LB_F16_SHIFTED}
 Q = 19
 
@@ -65,6 +67,7 @@ _SIGNATURES = [
                                       ctypes.POINTER(ctypes.c_int64)]),
     ("lb_timing_slots", ctypes.c_int32, []),
     ("lb_timing_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("lb_set_kernel", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lb_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
@@ -228,6 +231,11 @@ def lb_timing_name(slot: int) -> Optional[str]:
     return r.decode() if r is not None else None
 
 
+def lb_set_kernel(ctx, kernel) -> None:
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    _check(library().lb_set_kernel(ctx, k), "lb_set_kernel")
+
+
 def lb_device_bytes(ctx) -> int:
     b = ctypes.c_int64(0)
     _check(library().lb_device_bytes(ctx, ctypes.byref(b)), "lb_device_bytes")
@@ -245,7 +253,7 @@ class Lattice:
     """
 
     def __init__(self, shape, tau=(1.0, 1.0), G=0.0, psi_ref=1.0, storage="f64", rho0=(1.0, 1.0),
-                 device: int = 0, stream=None):
+                 device: int = 0, stream=None, kernel="auto"):
         nz, ny, nx = (int(s) for s in shape)
         p = lb_params_default()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -260,6 +268,7 @@ class Lattice:
         self.n = nx * ny * nz
         self.params = p
         self.ctx = lb_create(p)
+        lb_set_kernel(self.ctx, kernel)
 
     def close(self):
         if self.ctx is not None and self.ctx.value is not None:

@@ -34,11 +34,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def run_gpu(shape, tau, G, rho_a, rho_b, steps, u=None, solid=None, storage="f64"):
+KERNELS = ["fused", "two_pass"]
+
+
+def run_gpu(shape, tau, G, rho_a, rho_b, steps, u=None, solid=None, storage="f64", kernel="fused"):
     """Run ``steps`` steps through the C ABI and return the float64 populations [2][19][z][y][x]."""
     torch = _torch()
     n = int(np.prod(shape))
-    with P.Lattice(shape, tau=tau, G=G, storage=storage) as lat:
+    with P.Lattice(shape, tau=tau, G=G, storage=storage, kernel=kernel) as lat:
         uu = None if u is None else np.ascontiguousarray(np.stack(u).reshape(-1))
         lat.set_fields(np.ascontiguousarray(rho_a.reshape(-1)), np.ascontiguousarray(rho_b.reshape(-1)), uu,
                        None if solid is None else np.ascontiguousarray(solid.reshape(-1).astype(np.uint8)))
@@ -49,26 +52,28 @@ def run_gpu(shape, tau, G, rho_a, rho_b, steps, u=None, solid=None, storage="f64
         return f.cpu().numpy().reshape((2, 19) + tuple(shape))
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 7), (3, 1, 9), (1, 1, 1)])
-def test_f64_bitwise_equal_to_oracle_on_small_and_ragged_boxes(shape):
-    _say(f"case f64 bitwise shape={shape}")
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 7), (3, 1, 9), (1, 1, 1), (11, 19, 45), (9, 17, 64)])
+def test_f64_bitwise_equal_to_oracle_on_small_and_ragged_boxes(shape, kernel):
+    _say(f"case f64 bitwise shape={shape} kernel={kernel}")
     a, b = synth.fluid_fields(shape, 0.2, 21)
     rng = np.random.default_rng(22)
     u = [rng.uniform(-0.05, 0.05, shape) for _ in range(3)]
     p = O.Params((0.8, 1.3), 3.5)
     ref = O.step(O.init_equilibrium(a, b, u), p, n=5)
-    got = run_gpu(shape, p.tau, p.G, a, b, 5, u=u)
+    got = run_gpu(shape, p.tau, p.G, a, b, 5, u=u, kernel=kernel)
     assert O.population_error(got, ref) <= TOL_F64
     assert np.array_equal(got, ref), "float64 path is meant to reproduce the oracle bit for bit"
 
 
-def test_f64_mix32_200_steps_within_1e12():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_f64_mix32_200_steps_within_1e12(kernel):
     w = synth.WORKLOADS["mix32_f64"]
-    _say(f"case {w.name}")
+    _say(f"case {w.name} kernel={kernel}")
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
     p = O.Params(w.tau, w.G)
     ref = O.step(O.init_equilibrium(a, b), p, n=w.steps)
-    got = run_gpu(w.shape, w.tau, w.G, a, b, w.steps)
+    got = run_gpu(w.shape, w.tau, w.G, a, b, w.steps, kernel=kernel)
     err = O.population_error(got, ref)
     _say(f"  population error {err:.3e}, bit-identical fraction {np.mean(got == ref):.6f}")
     assert err <= TOL_F64
@@ -76,16 +81,17 @@ def test_f64_mix32_200_steps_within_1e12():
     assert np.ptp(O.density(ref[0])) > 0.5
 
 
-def test_f64_solids_match_oracle():
-    shape = (12, 14, 16)
-    _say(f"case f64 solids shape={shape}")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_f64_solids_match_oracle(kernel):
+    shape = (12, 14, 40)
+    _say(f"case f64 solids shape={shape} kernel={kernel}")
     centres = synth.sphere_centres(shape, 4, 2.5, 31)
     solid = synth.solid_mask(shape, centres, 2.5)
     assert 0 < solid.sum() < solid.size
     a, b = synth.fluid_fields(shape, 0.02, 32)
     p = O.Params((1.0, 0.9), 3.5)
     ref = O.step(O.init_equilibrium(a, b, solid=solid), p, solid, n=40)
-    got = run_gpu(shape, p.tau, p.G, a, b, 40, solid=solid)
+    got = run_gpu(shape, p.tau, p.G, a, b, 40, solid=solid, kernel=kernel)
     assert O.population_error(got, ref) <= TOL_F64
     assert np.array_equal(got, ref)
     assert np.all(got[:, :, solid.astype(bool)] == 0.0)
@@ -138,14 +144,15 @@ def test_conservation_on_gpu_over_many_steps():
     assert max(abs(v) for v in t1[2:]) / (t0[0] + t0[1]) < 1e-12
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("storage,tol_rho", [("f32", 1e-4), ("f16s", 2e-3)])
-def test_reduced_storage_error_against_oracle(storage, tol_rho):
+def test_reduced_storage_error_against_oracle(storage, tol_rho, kernel):
     w = synth.WORKLOADS["mix32_f64"]
-    _say(f"case {storage} vs oracle on {w.name} (100 steps)")
+    _say(f"case {storage} vs oracle on {w.name} (100 steps) kernel={kernel}")
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
     p = O.Params(w.tau, w.G)
     ref = O.step(O.init_equilibrium(a, b), p, n=100)
-    got = run_gpu(w.shape, w.tau, w.G, a, b, 100, storage=storage)
+    got = run_gpu(w.shape, w.tau, w.G, a, b, 100, storage=storage, kernel=kernel)
     drho = max(np.max(np.abs(O.density(got[k]) - O.density(ref[k]))) for k in range(2))
     _say(f"  max |drho| = {drho:.3e}")
     assert drho <= tol_rho
