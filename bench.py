@@ -109,8 +109,8 @@ def cpu_baseline(w, fields_fn):
     from oracle import lb_oracle as O
 
     nz, ny, nx = w.shape
-    planes = min(nz, 48)
-    steps = 2
+    planes = min(nz, 96)
+    steps = 4
     a, b = fields_fn()
     a = np.ascontiguousarray(a.reshape(w.shape)[:planes])
     b = np.ascontiguousarray(b.reshape(w.shape)[:planes])
