@@ -152,6 +152,52 @@ const char* lb_timing_name(int32_t slot);
 typedef enum { LB_KERNEL_AUTO = 0, LB_KERNEL_FUSED = 1, LB_KERNEL_TWO_PASS = 2 } lb_kernel;
 lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel);
 
+/* Change the Shan-Chen coupling G of later steps (and adjoint steps).
+ * Errors: LB_EINVAL (NULL, non-finite G). */
+lb_status lb_set_coupling(lb_ctx* ctx, double G);
+
+/* ---- Raw state snapshots (checkpointing) -------------------------------
+ * A snapshot is the current population grid in the library's own storage
+ * layout: lb_state_bytes() bytes, structure of arrays in the context's
+ * storage format.  It is meant only for lb_restore_state, lb_step_between
+ * and lb_adjoint_step of a context with the same parameters.
+ * lb_save_state copies the current state to dst; lb_restore_state makes src
+ * the current state.  on_device selects device or host memory.
+ * Errors: LB_EINVAL, LB_ESTATE (save before any state), LB_EDEVICE. */
+lb_status lb_state_bytes(const lb_ctx* ctx, int64_t* bytes);
+lb_status lb_save_state(lb_ctx* ctx, void* dst, int on_device);
+lb_status lb_restore_state(lb_ctx* ctx, const void* src, int on_device);
+
+/* One step from the snapshot at fin to the snapshot at fout, both device
+ * memory of lb_state_bytes() bytes, fin != fout; the context's own state is
+ * untouched.  Solid-node entries of fout are not written.  Enqueued on the
+ * context's stream.  Errors: LB_EINVAL, LB_EDEVICE. */
+lb_status lb_step_between(lb_ctx* ctx, const void* fin, void* fout);
+
+/* ---- Discrete adjoint (reverse-mode gradient of a final-state objective) --
+ * For an objective J of the densities after T steps, the caller
+ *   1. seeds lam(T) = dJ/df(T) from dJ/drho_A and dJ/drho_B at step T
+ *      (lb_adjoint_begin; float64 [N] each, NULL = zero), which also zeroes
+ *      the dJ/dG accumulator;
+ *   2. calls lb_adjoint_step once per step, last step first, each time with
+ *      the device snapshot of the pre-collision state f(t) that step started
+ *      from (t = T-1 down to 0), which maps lam(t+1) to lam(t) and adds the
+ *      step's part of dJ/dG: the transposed streaming (with bounce-back),
+ *      the transposed collision Jacobian including the velocity shift, and
+ *      the transposed Shan-Chen stencil;
+ *   3. reads dJ/drho_k(x, 0) = sum_i w_i lam_i^k(x, 0), the gradient with
+ *      respect to the densities of an initial state at rest (f = w_i rho_k,
+ *      Appendix Eq. LEQ with u = 0), and dJ/dG (lb_adjoint_result; any
+ *      output may be NULL).
+ * The adjoint's arithmetic type is the context's (float64 for LB_F64,
+ * float32 otherwise).  lb_adjoint_lambda exports lam as float64 [2][19][N].
+ * Errors: LB_EINVAL, LB_ESTATE (step or result before begin), LB_ENOMEM,
+ * LB_EDEVICE. */
+lb_status lb_adjoint_begin(lb_ctx* ctx, const double* dJ_drho_a, const double* dJ_drho_b, int on_device);
+lb_status lb_adjoint_step(lb_ctx* ctx, const void* state);
+lb_status lb_adjoint_result(lb_ctx* ctx, double* dJ_drho_a0, double* dJ_drho_b0, double* dJ_dG, int on_device);
+lb_status lb_adjoint_lambda(lb_ctx* ctx, double* lam, int on_device);
+
 /* Bytes of device memory the context holds. */
 lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes);
 

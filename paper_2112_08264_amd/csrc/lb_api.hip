@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "lb.h"
+#include "lb_adjoint.h"
 #include "lb_fused.h"
 #include "lb_kernels.h"
 
@@ -17,8 +18,16 @@ using namespace lbd;
 
 namespace {
 
-enum KernelSlot : int { SLOT_PSI = 0, SLOT_COLLIDE = 1, SLOT_FUSED = 2, SLOT_COUNT = 3 };
-const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused"};
+enum KernelSlot : int {
+  SLOT_PSI = 0,
+  SLOT_COLLIDE = 1,
+  SLOT_FUSED = 2,
+  SLOT_ADJ_MOMENTS = 3,
+  SLOT_ADJ_LOCAL = 4,
+  SLOT_ADJ_STENCIL = 5,
+  SLOT_COUNT = 6
+};
+const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused", "adj_moments", "adj_local", "adj_stencil"};
 constexpr int kFusedTY = 8;
 
 constexpr int kTotalsMaxBlocks = 2048;
@@ -51,8 +60,16 @@ struct lb_ctx {
   bool timing = false;
   std::vector<TimedLaunch> launches;
   std::vector<hipEvent_t> event_pool;
-  double t_ms[SLOT_COUNT] = {0, 0, 0};
-  int64_t t_n[SLOT_COUNT] = {0, 0, 0};
+  double t_ms[SLOT_COUNT] = {};
+  int64_t t_n[SLOT_COUNT] = {};
+  // adjoint buffers, allocated by lb_adjoint_begin
+  void* lam[2] = {nullptr, nullptr};  // [38][Npad] arithmetic type
+  int lam_cur = 0;
+  void* amom = nullptr;               // [10][N]
+  void* wbuf = nullptr;               // [6][N]
+  double* adj_partial = nullptr;      // per-block dJ/dG
+  double* adj_dG = nullptr;           // running dJ/dG
+  bool adj_ready = false;
   int kernel = LB_KERNEL_FUSED;
   FusedTiling tiling{};
   int64_t bytes = 0;
@@ -101,7 +118,9 @@ void free_all(lb_ctx* ctx) {
   ctx->launches.clear();
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   ctx->event_pool.clear();
-  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi, ctx->mask, ctx->partial, ctx->result, ctx->flag, ctx->plane};
+  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi,    ctx->mask,   ctx->partial,     ctx->result,
+                  ctx->flag,    ctx->plane,   ctx->lam[0], ctx->lam[1], ctx->amom,        ctx->wbuf,
+                  ctx->adj_partial, ctx->adj_dG};
   for (void* b : bufs)
     if (b != nullptr) (void)hipFree(b);
 }
@@ -284,6 +303,122 @@ lb_status totals_impl(lb_ctx* ctx, int blocks) {
   return LB_OK;
 }
 
+// One step from the raw state at fin to fout (both device, the context's layout).
+template <int ST>
+lb_status step_between_impl(lb_ctx* ctx, const void* fin, void* fout) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  const store* a = static_cast<const store*>(fin);
+  store* b = static_cast<store*>(fout);
+  const FusedTiling t = ctx->tiling;
+  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) {
+    return launch(ctx, SLOT_FUSED, [&] {
+      if constexpr (ST == ST_F64) {
+        if (ctx->has_solid)
+          k_fused_pair<ST, true, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, ctx->mask, ctx->g, ctx->c, t);
+        else
+          k_fused_pair<ST, false, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, nullptr, ctx->g, ctx->c, t);
+      } else {
+        if (ctx->has_solid)
+          k_fused<ST, true, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, ctx->mask, ctx->g, ctx->c, t);
+        else
+          k_fused<ST, false, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, nullptr, ctx->g, ctx->c, t);
+      }
+    });
+  }
+  const int nb = blocks_for(ctx->g.N);
+  real* psi = static_cast<real*>(ctx->psi);
+  const uint8_t* m = mask_or_null(ctx);
+  lb_status st = launch(ctx, SLOT_PSI, [&] {
+    if (m) k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(a, psi, m, ctx->g, ctx->c);
+    else k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(a, psi, nullptr, ctx->g, ctx->c);
+  });
+  if (st != LB_OK) return st;
+  return launch(ctx, SLOT_COLLIDE, [&] {
+    if (m) k_collide_push<ST, true><<<nb, kBlock, 0, ctx->stream>>>(a, b, psi, m, ctx->g, ctx->c);
+    else k_collide_push<ST, false><<<nb, kBlock, 0, ctx->stream>>>(a, b, psi, nullptr, ctx->g, ctx->c);
+  });
+}
+
+template <int ST>
+lb_status adjoint_alloc(lb_ctx* ctx) {
+  using real = typename StorageTraits<ST>::real;
+  if (ctx->adj_ready) return LB_OK;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  const size_t lam_bytes = sizeof(real) * static_cast<size_t>(2 * Q) * static_cast<size_t>(ctx->g.Npad);
+  lb_status st = LB_OK;
+  for (int b = 0; b < 2 && st == LB_OK; ++b) st = dev_alloc(ctx, &ctx->lam[b], lam_bytes);
+  if (st == LB_OK) st = dev_alloc(ctx, &ctx->amom, sizeof(real) * kAdjMom * N);
+  if (st == LB_OK) st = dev_alloc(ctx, &ctx->wbuf, sizeof(real) * 6 * N);
+  if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->adj_partial), sizeof(double) * blocks_for(ctx->g.N));
+  if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->adj_dG), sizeof(double) * 2);
+  if (st != LB_OK) return st;
+  // the padding of each plane is never written by the kernels; keep it zero
+  LB_HIP(hipMemsetAsync(ctx->lam[0], 0, lam_bytes, ctx->stream));
+  LB_HIP(hipMemsetAsync(ctx->lam[1], 0, lam_bytes, ctx->stream));
+  ctx->adj_ready = true;
+  return LB_OK;
+}
+
+template <int ST>
+lb_status adjoint_begin_impl(lb_ctx* ctx, const double* ga, const double* gb) {
+  using real = typename StorageTraits<ST>::real;
+  lb_status st = adjoint_alloc<ST>(ctx);
+  if (st != LB_OK) return st;
+  ctx->lam_cur = 0;
+  k_adj_seed<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ga, gb, mask_or_null(ctx),
+                                                                    static_cast<real*>(ctx->lam[0]), ctx->g);
+  LB_HIP(hipGetLastError());
+  LB_HIP(hipMemsetAsync(ctx->adj_dG, 0, sizeof(double) * 2, ctx->stream));
+  return LB_OK;
+}
+
+template <int ST>
+lb_status adjoint_step_impl(lb_ctx* ctx, const void* state) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  const int nb = blocks_for(ctx->g.N);
+  const uint8_t* m = mask_or_null(ctx);
+  real* mom = static_cast<real*>(ctx->amom);
+  real* W = static_cast<real*>(ctx->wbuf);
+  const real* lin = static_cast<const real*>(ctx->lam[ctx->lam_cur]);
+  real* lout = static_cast<real*>(ctx->lam[ctx->lam_cur ^ 1]);
+  lb_status st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
+    k_adj_moments<ST><<<nb, kBlock, 0, ctx->stream>>>(static_cast<const store*>(state), m, mom, ctx->g, ctx->c);
+  });
+  if (st != LB_OK) return st;
+  st = launch(ctx, SLOT_ADJ_LOCAL, [&] {
+    k_adj_local<ST><<<nb, kBlock, 0, ctx->stream>>>(lin, lout, mom, m, W, ctx->adj_partial, ctx->g, ctx->c);
+  });
+  if (st != LB_OK) return st;
+  st = launch(ctx, SLOT_ADJ_STENCIL, [&] {
+    k_adj_stencil<ST><<<nb, kBlock, 0, ctx->stream>>>(lout, mom, W, m, ctx->g, ctx->c);
+  });
+  if (st != LB_OK) return st;
+  k_adj_fold<<<1, kBlock, 0, ctx->stream>>>(ctx->adj_partial, nb, ctx->adj_dG);
+  LB_HIP(hipGetLastError());
+  ctx->lam_cur ^= 1;
+  return LB_OK;
+}
+
+template <int ST>
+lb_status adjoint_result_impl(lb_ctx* ctx, double* ga, double* gb) {
+  using real = typename StorageTraits<ST>::real;
+  k_adj_result<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const real*>(ctx->lam[ctx->lam_cur]),
+                                                                      ga, gb, ctx->g);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int ST>
+lb_status adjoint_export_impl(lb_ctx* ctx, double* out) {
+  using real = typename StorageTraits<ST>::real;
+  k_adj_export<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const real*>(ctx->lam[ctx->lam_cur]),
+                                                                      out, ctx->g);
+  LB_HIP(hipGetLastError());
+  return LB_OK;
+}
+
 template <typename F>
 lb_status by_storage(const lb_ctx* ctx, F&& f) {
   switch (ctx->p.storage) {
@@ -382,6 +517,8 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
     c.om[k] = 1.0 / p.tau[k];
     c.omc[k] = 1.0 - c.om[k];
     c.tg[k] = p.tau[k] * p.G;
+    c.tau[k] = p.tau[k];
+    c.tauf[k] = static_cast<float>(p.tau[k]);
     c.omf[k] = static_cast<float>(c.om[k]);
     c.omcf[k] = static_cast<float>(c.omc[k]);
     c.tgf[k] = static_cast<float>(c.tg[k]);
@@ -658,6 +795,159 @@ lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite) {
   const int nf = r[5] != 0.0 ? 1 : 0;
   if (nonfinite != nullptr) *nonfinite = nf;
   return nf ? LB_ENONFINITE : LB_OK;
+}
+
+lb_status lb_set_coupling(lb_ctx* ctx, double G) {
+  if (ctx == nullptr || !is_finite(G)) return LB_EINVAL;
+  ctx->p.G = G;
+  ctx->c.G = G;
+  ctx->c.Gf = static_cast<float>(G);
+  for (int k = 0; k < 2; ++k) {
+    ctx->c.tg[k] = ctx->p.tau[k] * G;
+    ctx->c.tgf[k] = static_cast<float>(ctx->c.tg[k]);
+  }
+  return LB_OK;
+}
+
+lb_status lb_state_bytes(const lb_ctx* ctx, int64_t* bytes) {
+  if (ctx == nullptr || bytes == nullptr) return LB_EINVAL;
+  *bytes = static_cast<int64_t>(ctx->grid_bytes);
+  return LB_OK;
+}
+
+lb_status lb_save_state(lb_ctx* ctx, void* dst, int on_device) {
+  if (ctx == nullptr || dst == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  LB_HIP(hipMemcpyAsync(dst, ctx->grid[ctx->cur], ctx->grid_bytes,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
+}
+
+lb_status lb_restore_state(lb_ctx* ctx, const void* src, int on_device) {
+  if (ctx == nullptr || src == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  if (!ctx->has_state) LB_HIP(hipMemsetAsync(ctx->grid[ctx->cur ^ 1], 0, ctx->grid_bytes, ctx->stream));
+  LB_HIP(hipMemcpyAsync(ctx->grid[ctx->cur], src, ctx->grid_bytes,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->has_state = true;
+  return LB_OK;
+}
+
+lb_status lb_step_between(lb_ctx* ctx, const void* fin, void* fout) {
+  if (ctx == nullptr || fin == nullptr || fout == nullptr || fin == fout) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  return by_storage(ctx, [&](auto tag) { return step_between_impl<decltype(tag)::value>(ctx, fin, fout); });
+}
+
+lb_status lb_adjoint_begin(lb_ctx* ctx, const double* dJ_drho_a, const double* dJ_drho_b, int on_device) {
+  if (ctx == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  const double* ga = dJ_drho_a;
+  const double* gb = dJ_drho_b;
+  void* tmp = nullptr;
+  if (!on_device && (ga != nullptr || gb != nullptr)) {
+    if (hipMalloc(&tmp, sizeof(double) * 2 * N) != hipSuccess) {
+      (void)hipGetLastError();
+      return LB_ENOMEM;
+    }
+    double* t = static_cast<double*>(tmp);
+    bool ok = true;
+    if (ga) ok = ok && hipMemcpyAsync(t, ga, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (gb) ok = ok && hipMemcpyAsync(t + N, gb, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      (void)hipFree(tmp);
+      return LB_EDEVICE;
+    }
+    ga = ga ? t : nullptr;
+    gb = gb ? t + N : nullptr;
+  }
+  lb_status st = by_storage(ctx, [&](auto tag) { return adjoint_begin_impl<decltype(tag)::value>(ctx, ga, gb); });
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && st == LB_OK) st = LB_EDEVICE;
+  if (tmp) (void)hipFree(tmp);
+  return st;
+}
+
+lb_status lb_adjoint_step(lb_ctx* ctx, const void* state) {
+  if (ctx == nullptr || state == nullptr) return LB_EINVAL;
+  if (!ctx->adj_ready) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  return by_storage(ctx, [&](auto tag) { return adjoint_step_impl<decltype(tag)::value>(ctx, state); });
+}
+
+lb_status lb_adjoint_result(lb_ctx* ctx, double* dJ_drho_a0, double* dJ_drho_b0, double* dJ_dG, int on_device) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (!ctx->adj_ready) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  lb_status st = LB_OK;
+  if (dJ_drho_a0 != nullptr || dJ_drho_b0 != nullptr) {
+    if (on_device) {
+      st = by_storage(ctx, [&](auto tag) { return adjoint_result_impl<decltype(tag)::value>(ctx, dJ_drho_a0, dJ_drho_b0); });
+    } else {
+      void* tmp = nullptr;
+      if (hipMalloc(&tmp, sizeof(double) * 2 * N) != hipSuccess) {
+        (void)hipGetLastError();
+        return LB_ENOMEM;
+      }
+      double* t = static_cast<double*>(tmp);
+      st = by_storage(ctx, [&](auto tag) { return adjoint_result_impl<decltype(tag)::value>(ctx, t, t + N); });
+      bool ok = st == LB_OK;
+      if (ok && dJ_drho_a0)
+        ok = hipMemcpyAsync(dJ_drho_a0, t, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+      if (ok && dJ_drho_b0)
+        ok = hipMemcpyAsync(dJ_drho_b0, t + N, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+      if (ok) ok = hipStreamSynchronize(ctx->stream) == hipSuccess;
+      (void)hipGetLastError();
+      (void)hipFree(tmp);
+      if (st == LB_OK && !ok) st = LB_EDEVICE;
+    }
+    if (st != LB_OK) return st;
+  }
+  if (dJ_dG != nullptr) {
+    double v = 0.0;
+    LB_HIP(hipMemcpyAsync(&v, ctx->adj_dG, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    LB_HIP(hipStreamSynchronize(ctx->stream));
+    *dJ_dG = v;
+  }
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
+}
+
+lb_status lb_adjoint_lambda(lb_ctx* ctx, double* lam, int on_device) {
+  if (ctx == nullptr || lam == nullptr) return LB_EINVAL;
+  if (!ctx->adj_ready) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t n = static_cast<size_t>(2 * Q) * static_cast<size_t>(ctx->g.N);
+  if (on_device) {
+    lb_status st = by_storage(ctx, [&](auto tag) { return adjoint_export_impl<decltype(tag)::value>(ctx, lam); });
+    if (st != LB_OK) return st;
+    LB_HIP(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+  }
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, sizeof(double) * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return LB_ENOMEM;
+  }
+  lb_status st = by_storage(ctx, [&](auto tag) { return adjoint_export_impl<decltype(tag)::value>(ctx, static_cast<double*>(tmp)); });
+  bool ok = st == LB_OK && hipMemcpyAsync(lam, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+            hipStreamSynchronize(ctx->stream) == hipSuccess;
+  (void)hipGetLastError();
+  (void)hipFree(tmp);
+  if (st != LB_OK) return st;
+  return ok ? LB_OK : LB_EDEVICE;
 }
 
 lb_status lb_timing(lb_ctx* ctx, int enable) {

@@ -55,9 +55,10 @@ struct StepCoeffs {
   double om[2];    // omega_k = 1 / tau_k
   double omc[2];   // 1 - omega_k
   double tg[2];    // tau_k * G
+  double tau[2];   // tau_k
   double G;
   double psi_ref;
-  float omf[2], omcf[2], tgf[2], Gf, psi_reff;
+  float omf[2], omcf[2], tgf[2], tauf[2], Gf, psi_reff;
   float shift[2][Q];  // w_i * rho0_k, the float16 storage offset
 };
 
@@ -133,6 +134,9 @@ template <> __device__ __forceinline__ float coef_omc<float>(const StepCoeffs& c
 template <typename real> __device__ __forceinline__ real coef_tg(const StepCoeffs& c, int k);
 template <> __device__ __forceinline__ double coef_tg<double>(const StepCoeffs& c, int k) { return c.tg[k]; }
 template <> __device__ __forceinline__ float coef_tg<float>(const StepCoeffs& c, int k) { return c.tgf[k]; }
+template <typename real> __device__ __forceinline__ real coef_tau(const StepCoeffs& c, int k);
+template <> __device__ __forceinline__ double coef_tau<double>(const StepCoeffs& c, int k) { return c.tau[k]; }
+template <> __device__ __forceinline__ float coef_tau<float>(const StepCoeffs& c, int k) { return c.tauf[k]; }
 template <typename real> __device__ __forceinline__ real coef_G(const StepCoeffs& c);
 template <> __device__ __forceinline__ double coef_G<double>(const StepCoeffs& c) { return c.G; }
 template <> __device__ __forceinline__ float coef_G<float>(const StepCoeffs& c) { return c.Gf; }

@@ -68,6 +68,15 @@ _SIGNATURES = [
     ("lb_timing_slots", ctypes.c_int32, []),
     ("lb_timing_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("lb_set_kernel", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lb_set_coupling", ctypes.c_int, [_P, ctypes.c_double]),
+    ("lb_state_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("lb_save_state", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb_restore_state", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb_step_between", ctypes.c_int, [_P, _P, _P]),
+    ("lb_adjoint_begin", ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    ("lb_adjoint_step", ctypes.c_int, [_P, _P]),
+    ("lb_adjoint_result", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
+    ("lb_adjoint_lambda", ctypes.c_int, [_P, _P, ctypes.c_int]),
     ("lb_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
@@ -234,6 +243,76 @@ def lb_timing_name(slot: int) -> Optional[str]:
 def lb_set_kernel(ctx, kernel) -> None:
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     _check(library().lb_set_kernel(ctx, k), "lb_set_kernel")
+
+
+def lb_set_coupling(ctx, G: float) -> None:
+    _check(library().lb_set_coupling(ctx, float(G)), "lb_set_coupling")
+
+
+def lb_state_bytes(ctx) -> int:
+    b = ctypes.c_int64(0)
+    _check(library().lb_state_bytes(ctx, ctypes.byref(b)), "lb_state_bytes")
+    return b.value
+
+
+def _raw(buf, nbytes: int, what: str):
+    """(pointer, on_device) of a contiguous byte buffer (uint8 tensor or NumPy array) of nbytes."""
+    mod = type(buf).__module__
+    if mod.startswith("torch"):
+        if not buf.is_contiguous() or buf.numel() * buf.element_size() != nbytes:
+            raise ValueError(f"{what}: need a contiguous buffer of {nbytes} bytes")
+        return ctypes.c_void_p(buf.data_ptr()), int(buf.is_cuda)
+    import numpy as np
+    if not isinstance(buf, np.ndarray) or not buf.flags["C_CONTIGUOUS"] or buf.nbytes != nbytes:
+        raise ValueError(f"{what}: need a contiguous buffer of {nbytes} bytes")
+    return ctypes.c_void_p(buf.ctypes.data), 0
+
+
+def lb_save_state(ctx, dst) -> None:
+    p, d = _raw(dst, lb_state_bytes(ctx), "dst")
+    _check(library().lb_save_state(ctx, p, d), "lb_save_state")
+
+
+def lb_restore_state(ctx, src) -> None:
+    p, d = _raw(src, lb_state_bytes(ctx), "src")
+    _check(library().lb_restore_state(ctx, p, d), "lb_restore_state")
+
+
+def lb_step_between(ctx, fin, fout) -> None:
+    nb = lb_state_bytes(ctx)
+    pi, di = _raw(fin, nb, "fin")
+    po, do = _raw(fout, nb, "fout")
+    if not (di and do):
+        raise ValueError("lb_step_between needs device buffers")
+    _check(library().lb_step_between(ctx, pi, po), "lb_step_between")
+
+
+def lb_adjoint_begin(ctx, n: int, dJ_drho_a=None, dJ_drho_b=None) -> None:
+    pa, da = _ptr(dJ_drho_a, "float64", n, "dJ_drho_a")
+    pb, db = _ptr(dJ_drho_b, "float64", n, "dJ_drho_b")
+    on_dev = _same_side(da if dJ_drho_a is not None else None, db if dJ_drho_b is not None else None)
+    _check(library().lb_adjoint_begin(ctx, pa, pb, on_dev), "lb_adjoint_begin")
+
+
+def lb_adjoint_step(ctx, state) -> None:
+    p, d = _raw(state, lb_state_bytes(ctx), "state")
+    if not d:
+        raise ValueError("lb_adjoint_step needs a device snapshot")
+    _check(library().lb_adjoint_step(ctx, p), "lb_adjoint_step")
+
+
+def lb_adjoint_result(ctx, n: int, dJ_drho_a0=None, dJ_drho_b0=None) -> float:
+    pa, da = _ptr(dJ_drho_a0, "float64", n, "dJ_drho_a0")
+    pb, db = _ptr(dJ_drho_b0, "float64", n, "dJ_drho_b0")
+    on_dev = _same_side(da if dJ_drho_a0 is not None else None, db if dJ_drho_b0 is not None else None)
+    g = ctypes.c_double(0.0)
+    _check(library().lb_adjoint_result(ctx, pa, pb, ctypes.byref(g), on_dev), "lb_adjoint_result")
+    return g.value
+
+
+def lb_adjoint_lambda(ctx, n: int, lam) -> None:
+    p, d = _ptr(lam, "float64", 2 * Q * n, "lam")
+    _check(library().lb_adjoint_lambda(ctx, p, d), "lb_adjoint_lambda")
 
 
 def lb_device_bytes(ctx) -> int:

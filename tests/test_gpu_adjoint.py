@@ -1,0 +1,200 @@
+"""GPU discrete adjoint (through the C ABI) against the FP64 oracle adjoint and
+against central finite differences of the GPU forward step."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2112_08264_amd as P
+from paper_2112_08264_amd import autograd as AG
+from oracle import lb_adjoint as A
+from oracle import lb_oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _state(shape, seed, amp=0.3, solid=None):
+    rng = np.random.default_rng(seed)
+    a, b = synth.fluid_fields(shape, amp, seed)
+    u = [rng.uniform(-0.04, 0.04, shape) for _ in range(3)]
+    f = O.init_equilibrium(a, b, u, solid=solid)
+    f = f * (1.0 + rng.uniform(-0.05, 0.05, f.shape))
+    if solid is not None:
+        f[:, :, solid.astype(bool)] = 0.0
+    return f
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 2e-4)])
+@pytest.mark.parametrize("with_solid", [False, True])
+def test_adjoint_steps_match_oracle(storage, tol, with_solid):
+    torch = _torch()
+    shape = (5, 6, 7)
+    n = int(np.prod(shape))
+    solid = None
+    if with_solid:
+        solid = np.zeros(shape, np.uint8)
+        solid[1, 2, 3] = solid[2, 2, 3] = solid[3, 4, 1] = 1
+    _say(f"case adjoint steps {storage} solid={with_solid}")
+    p = O.Params((0.8, 1.3), 3.5)
+    states = [_state(shape, 10 + t, solid=solid) for t in range(3)]
+    rng = np.random.default_rng(3)
+    ga, gb = rng.standard_normal(shape), rng.standard_normal(shape)
+    lam = A.density_gradient_seed(ga, gb, solid)
+    dG_ref = 0.0
+    with P.Lattice(shape, tau=p.tau, G=p.G, storage=storage) as lat:
+        a0, b0 = synth.fluid_fields(shape, 0.02, 1)
+        lat.set_fields(a0.ravel().copy(), b0.ravel().copy(), None,
+                       None if solid is None else solid.ravel().copy())
+        nb = P.lb_state_bytes(lat.ctx)
+        snaps = []
+        for f in states:
+            lat.set_populations(np.ascontiguousarray(f.ravel()))
+            buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            P.lb_save_state(lat.ctx, buf)
+            snaps.append(buf)
+        P.lb_adjoint_begin(lat.ctx, n, ga.ravel().copy(), gb.ravel().copy())
+        for t in range(2, -1, -1):
+            P.lb_adjoint_step(lat.ctx, snaps[t])
+            # the oracle works on the state as the GPU stores it (rounded to float32 for f32)
+            f_t = states[t].astype(np.float32).astype(np.float64) if storage == "f32" else states[t]
+            lam, dg = A.adjoint_step(f_t, lam, p, solid)
+            dG_ref += dg
+            got = np.empty(2 * 19 * n)
+            P.lb_adjoint_lambda(lat.ctx, n, got)
+            got = got.reshape(lam.shape)
+            scale = np.max(np.abs(lam))
+            assert np.max(np.abs(got - lam)) <= tol * scale, (t, np.max(np.abs(got - lam)) / scale)
+        r_a, r_b = np.empty(n), np.empty(n)
+        dG = P.lb_adjoint_result(lat.ctx, n, r_a, r_b)
+    wa, wb = A.initial_density_gradient(lam)
+    np.testing.assert_allclose(r_a.reshape(shape), wa, atol=tol * np.max(np.abs(wa)))
+    np.testing.assert_allclose(r_b.reshape(shape), wb, atol=tol * np.max(np.abs(wb)))
+    assert abs(dG - dG_ref) <= tol * max(1.0, abs(dG_ref)) * 10
+
+
+def _gpu_gradient(shape, a, b, target, tau, G, steps, every, storage, solid=None):
+    torch = _torch()
+    ra = torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+    rb = torch.tensor(b, dtype=torch.float64, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    sol = None if solid is None else torch.tensor(solid, dtype=torch.uint8, device="cuda")
+    spec = AG.Spec(shape=shape, tau=tau, steps=steps, every=every, storage=storage, solid=sol)
+    out = AG.final_density(ra, Gt, rb, spec)
+    t = torch.tensor(target, dtype=torch.float64, device="cuda")
+    d = out - t
+    if sol is not None:
+        d = torch.where(sol.bool(), torch.zeros_like(d), d)
+    J = (d * d).sum()
+    J.backward()
+    return float(J), ra.grad.cpu().numpy(), rb.grad.cpu().numpy(), float(Gt.grad)
+
+
+@pytest.mark.parametrize("with_solid", [False, True])
+def test_checkpointed_gradient_matches_oracle_gradient(with_solid):
+    shape = (6, 7, 9)
+    steps, every = 23, 5  # several segments, the last one partial
+    solid = None
+    if with_solid:
+        solid = synth.solid_mask(shape, np.array([[3.0, 3.5, 2.5]]), 1.6)
+    _say(f"case checkpointed gradient solid={with_solid}")
+    p = O.Params((1.0, 0.9), 3.5)
+    a, b = synth.fluid_fields(shape, 0.02, 5)
+    target = synth.smooth_target(shape, 6)
+    J_ref, ga_ref, gb_ref, dG_ref = A.gradient(a, b, target, p, steps, solid)
+    J, ga, gb, dG = _gpu_gradient(shape, a, b, target, p.tau, p.G, steps, every, "f64", solid)
+    assert abs(J - J_ref) <= 1e-12 * abs(J_ref)
+    s = np.max(np.abs(ga_ref))
+    assert np.max(np.abs(ga - ga_ref)) <= 1e-10 * s
+    assert np.max(np.abs(gb - gb_ref)) <= 1e-10 * np.max(np.abs(gb_ref))
+    assert abs(dG - dG_ref) <= 1e-10 * abs(dG_ref)
+
+
+def test_float32_gradient_close_to_oracle():
+    shape = (8, 8, 8)
+    steps, every = 20, 7
+    p = O.Params((1.0, 1.0), 3.5)
+    a, b = synth.fluid_fields(shape, 0.02, 15)
+    target = synth.smooth_target(shape, 16)
+    _say("case f32 gradient")
+    _, ga_ref, _, dG_ref = A.gradient(a, b, target, p, steps)
+    _, ga, _, dG = _gpu_gradient(shape, a, b, target, p.tau, p.G, steps, every, "f32")
+    rel = np.max(np.abs(ga - ga_ref)) / np.max(np.abs(ga_ref))
+    _say(f"  float32 gradient max relative error {rel:.2e}, dG {dG:.6e} vs {dG_ref:.6e}")
+    assert rel < 1e-3
+    assert abs(dG - dG_ref) < 1e-3 * abs(dG_ref)
+
+
+def test_gradient_against_central_differences_of_the_gpu_forward():
+    torch = _torch()
+    shape = (10, 10, 12)
+    steps, every = 30, 8
+    p = O.Params((1.0, 1.0), 3.5)
+    a, b = synth.fluid_fields(shape, 0.02, 25)
+    target = synth.smooth_target(shape, 26)
+    _say("case gradient vs central differences (GPU float64 forward)")
+    J, ga, gb, dG = _gpu_gradient(shape, a, b, target, p.tau, p.G, steps, every, "f64")
+
+    def J_of(ra, G=p.G):
+        n = ra.size
+        with P.Lattice(shape, tau=p.tau, G=G, storage="f64") as lat:
+            lat.set_fields(ra.ravel().copy(), b.ravel().copy())
+            lat.step(steps)
+            r = np.empty(n)
+            lat.moments(rho_a=r)
+        d = r.reshape(shape) - target
+        return float(np.sum((d * d).astype(np.float64)))
+
+    for (x, y, z) in synth.sample_sites(shape, 8, 27):
+        fds = []
+        for h in (1e-5, 5e-6):
+            ap, am = a.copy(), a.copy()
+            ap[z, y, x] += h
+            am[z, y, x] -= h
+            fds.append((J_of(ap) - J_of(am)) / (2 * h))
+        assert abs(fds[0] - fds[1]) <= 1e-7 * max(1e-3, abs(fds[1]))
+        assert abs(fds[1] - ga[z, y, x]) <= 1e-6 * max(1e-3, abs(fds[1])), ((x, y, z), fds[1], ga[z, y, x])
+    h = 1e-6
+    fdG = (J_of(a, p.G + h) - J_of(a, p.G - h)) / (2 * h)
+    assert abs(fdG - dG) <= 1e-6 * abs(fdG)
+
+
+def test_recompute_reproduces_forward_states_bitwise():
+    torch = _torch()
+    shape = (8, 9, 33)
+    n = int(np.prod(shape))
+    a, b = synth.fluid_fields(shape, 0.02, 35)
+    with P.Lattice(shape, tau=(0.8, 0.8), G=3.5, storage="f32") as lat:
+        lat.set_fields(a.ravel().copy(), b.ravel().copy())
+        nb = P.lb_state_bytes(lat.ctx)
+        s0 = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        P.lb_save_state(lat.ctx, s0)
+        lat.step(3)
+        s_ref = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        P.lb_save_state(lat.ctx, s_ref)
+        s1 = torch.empty_like(s0)
+        s2 = torch.empty_like(s0)
+        s3 = torch.empty_like(s0)
+        P.lb_step_between(lat.ctx, s0, s1)
+        P.lb_step_between(lat.ctx, s1, s2)
+        P.lb_step_between(lat.ctx, s2, s3)
+        torch.cuda.synchronize()
+        # compare the populations only (the plane padding is never written)
+        f_ref = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        f_new = torch.empty_like(f_ref)
+        lat.get_populations(f_ref)
+        P.lb_restore_state(lat.ctx, s3)
+        lat.get_populations(f_new)
+        assert torch.equal(f_ref, f_new)
