@@ -83,6 +83,48 @@ def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel
             "mass_drift": mass_drift}
 
 
+def adjoint_run(P, torch, synth, every: int = 50):
+    """Forward (with checkpoint saves) and backward (recompute + adjoint) of
+    J = sum (rho_A(T) - target)^2 on the 128^3 float32 gradient workload."""
+    from paper_2112_08264_amd import autograd as AG
+
+    w = synth.WORKLOADS["adjoint128_f32"]
+    a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+    target = torch.tensor(synth.smooth_target(w.shape, 4), device="cuda")
+    spec = AG.Spec(shape=w.shape, tau=w.tau, steps=w.steps, every=every, storage=w.storage)
+
+    def once():
+        ra = torch.tensor(a, device="cuda", requires_grad=True)
+        rb = torch.tensor(b, device="cuda")
+        G = torch.tensor(w.G, dtype=torch.float64, requires_grad=True)
+        out = AG.final_density(ra, G, rb, spec)
+        J = ((out - target) ** 2).sum()
+        J.backward()
+        return float(J), float(G.grad), float(ra.grad.abs().max())
+
+    once()  # warm-up (allocations, code objects)
+    J, dG, gmax = once()
+    fwd, bwd = AG.timings.forward_ms, AG.timings.backward_ms
+    # plain forward steps for reference
+    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=w.storage, device=0)
+    try:
+        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
+        lat.step(10)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.step(w.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        plain = e0.elapsed_time(e1)
+    finally:
+        lat.close()
+    return {"workload": w.name, "steps": w.steps, "checkpoint_every": every, "forward_ms": round(fwd, 3),
+            "backward_ms": round(bwd, 3), "ratio": round(bwd / fwd, 3), "plain_forward_ms": round(plain, 3),
+            "J": J, "dJ_dG": dG, "max_abs_dJ_drhoA0": gmax}
+
+
 def copy_calibration(torch, nbytes: int = 2 << 30, reps: int = 5):
     """Plain device-to-device copy of a known size: the reference kernel for
     scaling rocprofv3's FETCH_SIZE / WRITE_SIZE and for attainable bandwidth."""
@@ -156,6 +198,7 @@ def main(argv=None) -> int:
     ap.add_argument("--form-steps", type=int, default=200, help="timed steps of the float32 / float16 forms")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--calibrate", action="store_true",
                     help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
@@ -215,6 +258,12 @@ def main(argv=None) -> int:
                          "vs_f64": round(g / glups, 3) if w.storage == "f64" else None,
                          "nonfinite": r["nonfinite"], "kernels": r["kernels"]}
 
+    adjoint = None
+    if not args.no_adjoint:
+        log("bench: adjoint 128^3 float32, 500 steps, checkpoint every 50")
+        adjoint = adjoint_run(P, torch, synth)
+        log(f"bench: adjoint {adjoint}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -240,7 +289,8 @@ def main(argv=None) -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": None if adjoint is None else adjoint["ratio"],
+        "adjoint": adjoint,
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),

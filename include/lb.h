@@ -198,6 +198,19 @@ lb_status lb_adjoint_step(lb_ctx* ctx, const void* state);
 lb_status lb_adjoint_result(lb_ctx* ctx, double* dJ_drho_a0, double* dJ_drho_b0, double* dJ_dG, int on_device);
 lb_status lb_adjoint_lambda(lb_ctx* ctx, double* lam, int on_device);
 
+/* The adjoint needs, per step, only the moments of f(t): rho_A, rho_B,
+ * m_A (3), m_B (3), psi_A, psi_B, each [N] in the context's arithmetic type
+ * (a "record" of lb_record_bytes() bytes, zero at solid nodes).
+ * lb_step_record advances the context's own state by one step, exactly as
+ * lb_step(ctx, 1), and writes the record of the state it started from into
+ * device memory; lb_adjoint_step_record is lb_adjoint_step with that record
+ * in place of the snapshot.  A checkpointed backward pass restores a
+ * checkpoint, records the segment's steps and runs the adjoint over the
+ * records in reverse.  Errors: LB_EINVAL, LB_ESTATE, LB_EDEVICE. */
+lb_status lb_record_bytes(const lb_ctx* ctx, int64_t* bytes);
+lb_status lb_step_record(lb_ctx* ctx, void* record);
+lb_status lb_adjoint_step_record(lb_ctx* ctx, const void* record);
+
 /* Bytes of device memory the context holds. */
 lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes);
 

@@ -9,13 +9,14 @@ this module only drives them:
 * forward: lb_set_fields, then the steps, saving a raw state snapshot every
   ``spec.every`` steps (device memory, one grid per checkpoint);
 * backward: seed lam(T) = dJ/drho(T) (lb_adjoint_begin); for each segment,
-  last first, recompute its states from the checkpoint straight into
-  snapshot buffers (lb_step_between, no copies) and run the adjoint steps in
-  reverse over them (lb_adjoint_step); finally read dJ/drho(0) and dJ/dG
-  (lb_adjoint_result).
+  last first, restore its checkpoint and recompute its steps with
+  lb_step_record, which writes the moment record (rho, m, psi: 10 values per
+  node) the adjoint needs instead of the whole state, then run the adjoint
+  steps in reverse over the records (lb_adjoint_step_record); finally read
+  dJ/drho(0) and dJ/dG (lb_adjoint_result).
 
-Memory: one snapshot per checkpoint plus ``spec.every`` snapshots for the
-segment being recomputed.
+Memory: one state snapshot per checkpoint plus ``spec.every`` moment records
+for the segment being recomputed.
 """
 
 from __future__ import annotations
@@ -89,15 +90,16 @@ class FinalDensity(torch.autograd.Function):
         e0, e1 = _event(), _event()
         e0.record()
         L.lb_adjoint_begin(lat.ctx, n, grad_out.detach().contiguous().view(-1).to(torch.float64), None)
-        seg_bufs = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(max(0, spec.every - 1))]
+        rbytes = L.lb_record_bytes(lat.ctx)
+        recs = [torch.empty(rbytes, dtype=torch.uint8, device=dev) for _ in range(min(spec.every, spec.steps))]
         for seg in range(len(ckpts) - 1, -1, -1):
             s0 = seg * spec.every
             length = min(spec.every, spec.steps - s0)
-            snaps = [ckpts[seg]] + seg_bufs[: length - 1]
-            for t in range(1, length):
-                L.lb_step_between(lat.ctx, snaps[t - 1], snaps[t])
+            L.lb_restore_state(lat.ctx, ckpts[seg])
+            for t in range(length):
+                L.lb_step_record(lat.ctx, recs[t])
             for t in range(length - 1, -1, -1):
-                L.lb_adjoint_step(lat.ctx, snaps[t])
+                L.lb_adjoint_step_record(lat.ctx, recs[t])
         ga = torch.empty(n, dtype=torch.float64, device=dev)
         gb = torch.empty(n, dtype=torch.float64, device=dev)
         dG = L.lb_adjoint_result(lat.ctx, n, ga, gb)

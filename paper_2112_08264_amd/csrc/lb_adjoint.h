@@ -14,8 +14,12 @@
 //                - (V_k . S_k) tau_k G g'(rho_k) + c_j . (om_k U / D)
 //                - psi'(rho_k) sum_l w_l c_l . W_kbar(x - c_l)
 //   dJ/dG     += -sum_k (V_k . S_k) tau_k g(rho_k),   g = psi / rho.
-// Three kernels: moments of f(t); the local part (everything but the last
-// line, which needs W of the neighbours); the stencil part.
+// lam is kept in two parts, lam_j^k(x) = P_j^k(x) + r_k(x): P holds the
+// local terms and r_k(x) = -psi'(rho_k(x)) sum_l w_l c_l . W_kbar(x - c_l)
+// the stencil term, which is the same for every direction.  One adjoint step
+// is then the local kernel (reads P and r of t+1 pulled from x + c_i, writes
+// P(t) and W) and a small kernel that turns W into r(t); the moments of f(t)
+// come either from a record the forward step wrote or from k_adj_moments.
 #pragma once
 
 #include "lb_kernels.h"
@@ -70,8 +74,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_moments(const store_t<ST>* __res
 // Local part.  lam_in = lam(t+1), lam_out = lam(t) without the stencil term;
 // W = [6][N] (W_A then W_B); partial[block] = the block's dJ/dG sum (float64).
 template <int ST>
-__global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restrict__ lam_in, real_t<ST>* __restrict__ lam_out,
-                                                      const real_t<ST>* __restrict__ mom,
+__global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restrict__ lam_in, const real_t<ST>* __restrict__ r_in,
+                                                      real_t<ST>* __restrict__ lam_out, const real_t<ST>* __restrict__ mom,
                                                       const uint8_t* __restrict__ mask, real_t<ST>* __restrict__ Wout,
                                                       double* __restrict__ partial, Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
@@ -138,8 +142,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restri
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           long long src = (long long)(k * Q + i) * g.Npad + nb[i];
-          if (i != 0 && mask != nullptr && mask[nb[i]]) src = (long long)(k * Q + OPP[i]) * g.Npad + n;
-          const real ai = lam_in[src];
+          long long rsrc = (long long)k * g.N + nb[i];
+          if (i != 0 && mask != nullptr && mask[nb[i]]) {
+            src = (long long)(k * Q + OPP[i]) * g.Npad + n;
+            rsrc = (long long)k * g.N + n;
+          }
+          const real ai = lam_in[src] + r_in[rsrc];
           am[k][i] = ai;
           const real cu = real(CX[i]) * v[k][0] + real(CY[i]) * v[k][1] + real(CZ[i]) * v[k][2];
           const real E = real(1) + real(3) * cu + real(4.5) * cu * cu - real(1.5) * vv;
@@ -186,18 +194,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restri
   }
 }
 
-// Stencil part: lam(t) += -psi'(rho_k) sum_l w_l c_l . W_kbar(x - c_l) on every direction of component k.
+// Stencil term r_k(x) = -psi'(rho_k(x)) sum_l w_l c_l . W_kbar(x - c_l), zero at solid nodes.
 template <int ST>
-__global__ void __launch_bounds__(kBlock) k_adj_stencil(real_t<ST>* __restrict__ lam, const real_t<ST>* __restrict__ mom,
-                                                        const real_t<ST>* __restrict__ Win,
-                                                        const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c) {
+__global__ void __launch_bounds__(kBlock) k_adj_r(const real_t<ST>* __restrict__ mom, const real_t<ST>* __restrict__ Win,
+                                                  const uint8_t* __restrict__ mask, real_t<ST>* __restrict__ r,
+                                                  Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
-  if (mask != nullptr && mask[n]) return;
+  if (mask != nullptr && mask[n]) {
+    r[n] = real(0);
+    r[(long long)g.N + n] = real(0);
+    return;
+  }
   int x, y, z;
   node_xyz(n, g, x, y, z);
-  // nodes x - c_l: the neighbour table of x + c_l read with the opposite index
   int nb[Q];
   neighbours(x, y, z, g, nb);
   const real ref = coef_ref<real>(c);
@@ -208,14 +219,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_stencil(real_t<ST>* __restrict__
 #pragma unroll
     for (int l = 1; l < Q; ++l) {
       const long long src = nb[OPP[l]];  // x - c_l
-      const real wc = weight<real>(l);
-      T += wc * (real(CX[l]) * Win[(long long)(3 * kb + 0) * g.N + src] + real(CY[l]) * Win[(long long)(3 * kb + 1) * g.N + src] +
-                 real(CZ[l]) * Win[(long long)(3 * kb + 2) * g.N + src]);
+      T += weight<real>(l) * (real(CX[l]) * Win[(long long)(3 * kb + 0) * g.N + src] +
+                              real(CY[l]) * Win[(long long)(3 * kb + 1) * g.N + src] +
+                              real(CZ[l]) * Win[(long long)(3 * kb + 2) * g.N + src]);
     }
     const real rho = mom[(long long)k * g.N + n];
-    const real r = -exp_real<real>(-rho / ref) * T;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) lam[(long long)(k * Q + j) * g.Npad + n] += r;
+    r[(long long)k * g.N + n] = -exp_real<real>(-rho / ref) * T;
   }
 }
 
@@ -237,10 +246,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
 // lam(T) seed: lam_i^k(x) = dJ/drho_k(x) (0 at solid nodes).
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_adj_seed(const double* __restrict__ ga, const double* __restrict__ gb,
-                                                     const uint8_t* __restrict__ mask, real* __restrict__ lam, Geometry g) {
+                                                     const uint8_t* __restrict__ mask, real* __restrict__ lam,
+                                                     real* __restrict__ r, Geometry g) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
   const bool solid = mask != nullptr && mask[n];
+  r[n] = real(0);
+  r[(long long)g.N + n] = real(0);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const real v = solid ? real(0) : static_cast<real>(k == 0 ? (ga ? ga[n] : 0.0) : (gb ? gb[n] : 0.0));
@@ -251,15 +263,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_seed(const double* __restrict__ 
 
 // dJ/drho_k(x, 0) = sum_i w_i lam_i^k(x, 0)
 template <typename real>
-__global__ void __launch_bounds__(kBlock) k_adj_result(const real* __restrict__ lam, double* __restrict__ ga,
-                                                       double* __restrict__ gb, Geometry g) {
+__global__ void __launch_bounds__(kBlock) k_adj_result(const real* __restrict__ lam, const real* __restrict__ r,
+                                                       double* __restrict__ ga, double* __restrict__ gb, Geometry g) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     double s = 0.0;
+    const double rk = static_cast<double>(r[(long long)k * g.N + n]);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s += weight<double>(i) * static_cast<double>(lam[(long long)(k * Q + i) * g.Npad + n]);
+    for (int i = 0; i < Q; ++i)
+      s += weight<double>(i) * (static_cast<double>(lam[(long long)(k * Q + i) * g.Npad + n]) + rk);
     double* out = k == 0 ? ga : gb;
     if (out) out[n] = s;
   }
@@ -267,10 +281,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_result(const real* __restrict__ 
 
 // lam as float64 [2][19][N] (for inspection and tests)
 template <typename real>
-__global__ void __launch_bounds__(kBlock) k_adj_export(const real* __restrict__ lam, double* __restrict__ out, Geometry g) {
+__global__ void __launch_bounds__(kBlock) k_adj_export(const real* __restrict__ lam, const real* __restrict__ r,
+                                                       double* __restrict__ out, Geometry g) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
-  for (int p = 0; p < 2 * Q; ++p) out[(long long)p * g.N + n] = static_cast<double>(lam[(long long)p * g.Npad + n]);
+  for (int p = 0; p < 2 * Q; ++p)
+    out[(long long)p * g.N + n] =
+        static_cast<double>(lam[(long long)p * g.Npad + n]) + static_cast<double>(r[(long long)(p / Q) * g.N + n]);
 }
 
 }  // namespace lbd

@@ -24,10 +24,10 @@ enum KernelSlot : int {
   SLOT_FUSED = 2,
   SLOT_ADJ_MOMENTS = 3,
   SLOT_ADJ_LOCAL = 4,
-  SLOT_ADJ_STENCIL = 5,
+  SLOT_ADJ_R = 5,
   SLOT_COUNT = 6
 };
-const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused", "adj_moments", "adj_local", "adj_stencil"};
+const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused", "adj_moments", "adj_local", "adj_r"};
 constexpr int kFusedTY = 8;
 
 constexpr int kTotalsMaxBlocks = 2048;
@@ -67,6 +67,7 @@ struct lb_ctx {
   int lam_cur = 0;
   void* amom = nullptr;               // [10][N]
   void* wbuf = nullptr;               // [6][N]
+  void* rbuf = nullptr;               // [2][N] stencil term of lam
   double* adj_partial = nullptr;      // per-block dJ/dG
   double* adj_dG = nullptr;           // running dJ/dG
   bool adj_ready = false;
@@ -120,7 +121,7 @@ void free_all(lb_ctx* ctx) {
   ctx->event_pool.clear();
   void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi,    ctx->mask,   ctx->partial,     ctx->result,
                   ctx->flag,    ctx->plane,   ctx->lam[0], ctx->lam[1], ctx->amom,        ctx->wbuf,
-                  ctx->adj_partial, ctx->adj_dG};
+                  ctx->rbuf,    ctx->adj_partial, ctx->adj_dG};
   for (void* b : bufs)
     if (b != nullptr) (void)hipFree(b);
 }
@@ -180,29 +181,45 @@ const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->ma
 // ---------------------------------------------------------------------------
 // Typed implementations
 // ---------------------------------------------------------------------------
+// One fused step from fin to fout.  float64: component-pair waves without
+// register prefetch (two planes of float64 populations fill the register
+// budget); float32 arithmetic: single-component waves with a prefetch depth
+// of three planes.  With rec != nullptr the kernel also writes the moment
+// record of the pre-collision state for the adjoint.
+template <int ST>
+lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
+                       typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
+  const FusedTiling t = ctx->tiling;
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  const dim3 grid(t.total), block(64 * kFusedTY);
+  return launch(ctx, SLOT_FUSED, [&] {
+    if constexpr (ST == ST_F64) {
+      if (m) {
+        if (rec) k_fused_pair<ST, true, kFusedTY, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        else k_fused_pair<ST, true, kFusedTY, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+      } else {
+        if (rec) k_fused_pair<ST, false, kFusedTY, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        else k_fused_pair<ST, false, kFusedTY, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+      }
+    } else {
+      if (m) {
+        if (rec) k_fused<ST, true, kFusedTY, 3, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        else k_fused<ST, true, kFusedTY, 3, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+      } else {
+        if (rec) k_fused<ST, false, kFusedTY, 3, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        else k_fused<ST, false, kFusedTY, 3, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+      }
+    }
+  });
+}
+
 template <int ST>
 lb_status fused_step_impl(lb_ctx* ctx, int n) {
   using store = typename StorageTraits<ST>::store_t;
-  const FusedTiling t = ctx->tiling;
   for (int s = 0; s < n; ++s) {
     const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
     store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
-    // float64: component-pair waves without register prefetch (two planes of
-    // float64 populations fill the register budget); float32 arithmetic:
-    // single-component waves with a prefetch depth of three planes.
-    lb_status st = launch(ctx, SLOT_FUSED, [&] {
-      if constexpr (ST == ST_F64) {
-        if (ctx->has_solid)
-          k_fused_pair<ST, true, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, ctx->mask, ctx->g, ctx->c, t);
-        else
-          k_fused_pair<ST, false, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t);
-      } else {
-        if (ctx->has_solid)
-          k_fused<ST, true, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, ctx->mask, ctx->g, ctx->c, t);
-        else
-          k_fused<ST, false, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t);
-      }
-    });
+    lb_status st = launch_fused<ST>(ctx, fin, fout, nullptr);
     if (st != LB_OK) return st;
     ctx->cur ^= 1;
   }
@@ -310,22 +327,7 @@ lb_status step_between_impl(lb_ctx* ctx, const void* fin, void* fout) {
   using real = typename StorageTraits<ST>::real;
   const store* a = static_cast<const store*>(fin);
   store* b = static_cast<store*>(fout);
-  const FusedTiling t = ctx->tiling;
-  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) {
-    return launch(ctx, SLOT_FUSED, [&] {
-      if constexpr (ST == ST_F64) {
-        if (ctx->has_solid)
-          k_fused_pair<ST, true, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, ctx->mask, ctx->g, ctx->c, t);
-        else
-          k_fused_pair<ST, false, kFusedTY><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, nullptr, ctx->g, ctx->c, t);
-      } else {
-        if (ctx->has_solid)
-          k_fused<ST, true, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, ctx->mask, ctx->g, ctx->c, t);
-        else
-          k_fused<ST, false, kFusedTY, 3><<<t.total, 64 * kFusedTY, 0, ctx->stream>>>(a, b, nullptr, ctx->g, ctx->c, t);
-      }
-    });
-  }
+  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) return launch_fused<ST>(ctx, a, b, nullptr);
   const int nb = blocks_for(ctx->g.N);
   real* psi = static_cast<real*>(ctx->psi);
   const uint8_t* m = mask_or_null(ctx);
@@ -350,6 +352,7 @@ lb_status adjoint_alloc(lb_ctx* ctx) {
   for (int b = 0; b < 2 && st == LB_OK; ++b) st = dev_alloc(ctx, &ctx->lam[b], lam_bytes);
   if (st == LB_OK) st = dev_alloc(ctx, &ctx->amom, sizeof(real) * kAdjMom * N);
   if (st == LB_OK) st = dev_alloc(ctx, &ctx->wbuf, sizeof(real) * 6 * N);
+  if (st == LB_OK) st = dev_alloc(ctx, &ctx->rbuf, sizeof(real) * 2 * N);
   if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->adj_partial), sizeof(double) * blocks_for(ctx->g.N));
   if (st == LB_OK) st = dev_alloc(ctx, reinterpret_cast<void**>(&ctx->adj_dG), sizeof(double) * 2);
   if (st != LB_OK) return st;
@@ -366,34 +369,28 @@ lb_status adjoint_begin_impl(lb_ctx* ctx, const double* ga, const double* gb) {
   lb_status st = adjoint_alloc<ST>(ctx);
   if (st != LB_OK) return st;
   ctx->lam_cur = 0;
-  k_adj_seed<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ga, gb, mask_or_null(ctx),
-                                                                    static_cast<real*>(ctx->lam[0]), ctx->g);
+  k_adj_seed<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+      ga, gb, mask_or_null(ctx), static_cast<real*>(ctx->lam[0]), static_cast<real*>(ctx->rbuf), ctx->g);
   LB_HIP(hipGetLastError());
   LB_HIP(hipMemsetAsync(ctx->adj_dG, 0, sizeof(double) * 2, ctx->stream));
   return LB_OK;
 }
 
+// One adjoint step given the moment record of f(t) (rho, m, psi as [10][N]).
 template <int ST>
-lb_status adjoint_step_impl(lb_ctx* ctx, const void* state) {
-  using store = typename StorageTraits<ST>::store_t;
+lb_status adjoint_record_step_impl(lb_ctx* ctx, const typename StorageTraits<ST>::real* mom) {
   using real = typename StorageTraits<ST>::real;
   const int nb = blocks_for(ctx->g.N);
   const uint8_t* m = mask_or_null(ctx);
-  real* mom = static_cast<real*>(ctx->amom);
   real* W = static_cast<real*>(ctx->wbuf);
+  real* r = static_cast<real*>(ctx->rbuf);
   const real* lin = static_cast<const real*>(ctx->lam[ctx->lam_cur]);
   real* lout = static_cast<real*>(ctx->lam[ctx->lam_cur ^ 1]);
-  lb_status st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
-    k_adj_moments<ST><<<nb, kBlock, 0, ctx->stream>>>(static_cast<const store*>(state), m, mom, ctx->g, ctx->c);
+  lb_status st = launch(ctx, SLOT_ADJ_LOCAL, [&] {
+    k_adj_local<ST><<<nb, kBlock, 0, ctx->stream>>>(lin, r, lout, mom, m, W, ctx->adj_partial, ctx->g, ctx->c);
   });
   if (st != LB_OK) return st;
-  st = launch(ctx, SLOT_ADJ_LOCAL, [&] {
-    k_adj_local<ST><<<nb, kBlock, 0, ctx->stream>>>(lin, lout, mom, m, W, ctx->adj_partial, ctx->g, ctx->c);
-  });
-  if (st != LB_OK) return st;
-  st = launch(ctx, SLOT_ADJ_STENCIL, [&] {
-    k_adj_stencil<ST><<<nb, kBlock, 0, ctx->stream>>>(lout, mom, W, m, ctx->g, ctx->c);
-  });
+  st = launch(ctx, SLOT_ADJ_R, [&] { k_adj_r<ST><<<nb, kBlock, 0, ctx->stream>>>(mom, W, m, r, ctx->g, ctx->c); });
   if (st != LB_OK) return st;
   k_adj_fold<<<1, kBlock, 0, ctx->stream>>>(ctx->adj_partial, nb, ctx->adj_dG);
   LB_HIP(hipGetLastError());
@@ -401,11 +398,47 @@ lb_status adjoint_step_impl(lb_ctx* ctx, const void* state) {
   return LB_OK;
 }
 
+// One adjoint step given a raw snapshot of f(t): moments first.
+template <int ST>
+lb_status adjoint_step_impl(lb_ctx* ctx, const void* state) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  real* mom = static_cast<real*>(ctx->amom);
+  lb_status st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
+    k_adj_moments<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const store*>(state),
+                                                                       mask_or_null(ctx), mom, ctx->g, ctx->c);
+  });
+  if (st != LB_OK) return st;
+  return adjoint_record_step_impl<ST>(ctx, mom);
+}
+
+// One forward step of the context's state that also writes the moment record of f(t).
+template <int ST>
+lb_status step_record_impl(lb_ctx* ctx, void* record) {
+  using store = typename StorageTraits<ST>::store_t;
+  using real = typename StorageTraits<ST>::real;
+  const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+  store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+  real* rec = static_cast<real*>(record);
+  lb_status st;
+  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) {
+    st = launch_fused<ST>(ctx, fin, fout, rec);
+  } else {
+    st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
+      k_adj_moments<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, mask_or_null(ctx), rec, ctx->g, ctx->c);
+    });
+    if (st == LB_OK) st = step_between_impl<ST>(ctx, fin, fout);
+  }
+  if (st != LB_OK) return st;
+  ctx->cur ^= 1;
+  return LB_OK;
+}
+
 template <int ST>
 lb_status adjoint_result_impl(lb_ctx* ctx, double* ga, double* gb) {
   using real = typename StorageTraits<ST>::real;
-  k_adj_result<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const real*>(ctx->lam[ctx->lam_cur]),
-                                                                      ga, gb, ctx->g);
+  k_adj_result<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+      static_cast<const real*>(ctx->lam[ctx->lam_cur]), static_cast<const real*>(ctx->rbuf), ga, gb, ctx->g);
   LB_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -413,8 +446,8 @@ lb_status adjoint_result_impl(lb_ctx* ctx, double* ga, double* gb) {
 template <int ST>
 lb_status adjoint_export_impl(lb_ctx* ctx, double* out) {
   using real = typename StorageTraits<ST>::real;
-  k_adj_export<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const real*>(ctx->lam[ctx->lam_cur]),
-                                                                      out, ctx->g);
+  k_adj_export<real><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+      static_cast<const real*>(ctx->lam[ctx->lam_cur]), static_cast<const real*>(ctx->rbuf), out, ctx->g);
   LB_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -843,6 +876,31 @@ lb_status lb_step_between(lb_ctx* ctx, const void* fin, void* fout) {
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
   return by_storage(ctx, [&](auto tag) { return step_between_impl<decltype(tag)::value>(ctx, fin, fout); });
+}
+
+lb_status lb_record_bytes(const lb_ctx* ctx, int64_t* bytes) {
+  if (ctx == nullptr || bytes == nullptr) return LB_EINVAL;
+  *bytes = static_cast<int64_t>(ctx->real_bytes) * kAdjMom * static_cast<int64_t>(ctx->g.N);
+  return LB_OK;
+}
+
+lb_status lb_step_record(lb_ctx* ctx, void* record) {
+  if (ctx == nullptr || record == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  return by_storage(ctx, [&](auto tag) { return step_record_impl<decltype(tag)::value>(ctx, record); });
+}
+
+lb_status lb_adjoint_step_record(lb_ctx* ctx, const void* record) {
+  if (ctx == nullptr || record == nullptr) return LB_EINVAL;
+  if (!ctx->adj_ready) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  return by_storage(ctx, [&](auto tag) {
+    using real = typename StorageTraits<decltype(tag)::value>::real;
+    return adjoint_record_step_impl<decltype(tag)::value>(ctx, static_cast<const real*>(record));
+  });
 }
 
 lb_status lb_adjoint_begin(lb_ctx* ctx, const double* dJ_drho_a, const double* dJ_drho_b, int on_device) {

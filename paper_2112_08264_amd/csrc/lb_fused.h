@@ -54,10 +54,13 @@ __device__ __forceinline__ int fused_work_item(int b, int total) {
   return j * q + (j < r ? j : r) + s;
 }
 
-template <int ST, bool SOLID, int TY, int D>
+// RECORD: also write the moment record of the pre-collision state (rho_A,
+// rho_B, m_A, m_B, psi_A, psi_B as [10][N], zero at solid nodes) that the
+// adjoint step consumes.
+template <int ST, bool SOLID, int TY, int D, bool RECORD>
 __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
                                                    const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c,
-                                                   FusedTiling t) {
+                                                   FusedTiling t, real_t<ST>* __restrict__ rec) {
   using real = real_t<ST>;
   using store = store_t<ST>;
   constexpr int TX = kFusedTX;
@@ -211,6 +214,16 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
     const real vz = up[2] - ak * S[2];
     const real vv = (vx * vx + vy * vy) + vz * vz;
     const real t15 = real(1.5) * vv;
+    if constexpr (RECORD) {
+      if (active) {
+        const size_t node = row + plane_n * (uint32_t)z;
+        const size_t Nn = (size_t)g.N;
+        rec[(size_t)k * Nn + node] = here_solid ? real(0) : rho_k;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rec[(size_t)(2 + 3 * k + a) * Nn + node] = here_solid ? real(0) : xch[par][k][1 + a][ly][lx];
+        rec[(size_t)(8 + k) * Nn + node] = psi_k;
+      }
+    }
     if (active && !here_solid) {
       const uint32_t Z[3] = {plane_n * (uint32_t)wrapz(z - 1), plane_n * (uint32_t)z, plane_n * (uint32_t)wrapz(z + 1)};
       const uint32_t here = row + Z[1];
@@ -255,11 +268,11 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
 // iteration, which keeps the float64 register budget (two planes of 19
 // populations) within 256 VGPRs without spilling.  Ring of three planes.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID, int TY>
+template <int ST, bool SOLID, int TY, bool RECORD>
 __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                         store_t<ST>* __restrict__ fout,
                                                         const uint8_t* __restrict__ mask, Geometry g,
-                                                        StepCoeffs c, FusedTiling t) {
+                                                        StepCoeffs c, FusedTiling t, real_t<ST>* __restrict__ rec) {
   using real = real_t<ST>;
   constexpr int TX = kFusedTX;
   constexpr int RX = TX + 2, RY = TY + 2;
@@ -382,6 +395,15 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
     const real vz = up[2] - ak * S[2];
     const real vv = (vx * vx + vy * vy) + vz * vz;
     const real t15 = real(1.5) * vv;
+    if constexpr (RECORD) {
+      if (active) {
+        const long long node = row + plane_n * z;
+        rec[(long long)k * g.N + node] = here_solid ? real(0) : rho_k;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rec[(long long)(2 + 3 * k + a) * g.N + node] = here_solid ? real(0) : m_k[a];
+        rec[(long long)(8 + k) * g.N + node] = psi_k;
+      }
+    }
 
     if (active && !here_solid) {
       const int zm = wrapz(z - 1), zp = wrapz(z + 1);

@@ -77,6 +77,9 @@ _SIGNATURES = [
     ("lb_adjoint_step", ctypes.c_int, [_P, _P]),
     ("lb_adjoint_result", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     ("lb_adjoint_lambda", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb_record_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("lb_step_record", ctypes.c_int, [_P, _P]),
+    ("lb_adjoint_step_record", ctypes.c_int, [_P, _P]),
     ("lb_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
@@ -313,6 +316,26 @@ def lb_adjoint_result(ctx, n: int, dJ_drho_a0=None, dJ_drho_b0=None) -> float:
 def lb_adjoint_lambda(ctx, n: int, lam) -> None:
     p, d = _ptr(lam, "float64", 2 * Q * n, "lam")
     _check(library().lb_adjoint_lambda(ctx, p, d), "lb_adjoint_lambda")
+
+
+def lb_record_bytes(ctx) -> int:
+    b = ctypes.c_int64(0)
+    _check(library().lb_record_bytes(ctx, ctypes.byref(b)), "lb_record_bytes")
+    return b.value
+
+
+def lb_step_record(ctx, record) -> None:
+    p, d = _raw(record, lb_record_bytes(ctx), "record")
+    if not d:
+        raise ValueError("lb_step_record needs a device buffer")
+    _check(library().lb_step_record(ctx, p), "lb_step_record")
+
+
+def lb_adjoint_step_record(ctx, record) -> None:
+    p, d = _raw(record, lb_record_bytes(ctx), "record")
+    if not d:
+        raise ValueError("lb_adjoint_step_record needs a device buffer")
+    _check(library().lb_adjoint_step_record(ctx, p), "lb_adjoint_step_record")
 
 
 def lb_device_bytes(ctx) -> int:

@@ -198,3 +198,45 @@ def test_recompute_reproduces_forward_states_bitwise():
         P.lb_restore_state(lat.ctx, s3)
         lat.get_populations(f_new)
         assert torch.equal(f_ref, f_new)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_record_path_equals_snapshot_path(storage):
+    torch = _torch()
+    shape = (7, 9, 40)
+    n = int(np.prod(shape))
+    steps = 6
+    solid = synth.solid_mask(shape, np.array([[20.0, 4.0, 3.0]]), 2.2)
+    a, b = synth.fluid_fields(shape, 0.02, 45)
+    g0 = np.random.default_rng(46).standard_normal(shape)
+    _say(f"case record vs snapshot adjoint {storage}")
+    results = []
+    for use_record in (False, True):
+        with P.Lattice(shape, tau=(0.9, 1.1), G=3.5, storage=storage) as lat:
+            lat.set_fields(a.ravel().copy(), b.ravel().copy(), None, solid.ravel().copy())
+            nb, rb = P.lb_state_bytes(lat.ctx), P.lb_record_bytes(lat.ctx)
+            snaps, recs = [], []
+            for t in range(steps):
+                if use_record:
+                    r = torch.empty(rb, dtype=torch.uint8, device="cuda")
+                    P.lb_step_record(lat.ctx, r)
+                    recs.append(r)
+                else:
+                    s = torch.empty(nb, dtype=torch.uint8, device="cuda")
+                    P.lb_save_state(lat.ctx, s)
+                    snaps.append(s)
+                    lat.step(1)
+            P.lb_adjoint_begin(lat.ctx, n, g0.ravel().copy(), None)
+            for t in range(steps - 1, -1, -1):
+                if use_record:
+                    P.lb_adjoint_step_record(lat.ctx, recs[t])
+                else:
+                    P.lb_adjoint_step(lat.ctx, snaps[t])
+            ga = np.empty(n)
+            dG = P.lb_adjoint_result(lat.ctx, n, ga)
+            f = np.empty(2 * 19 * n)
+            lat.get_populations(f)
+        results.append((ga, dG, f))
+    assert np.array_equal(results[0][2], results[1][2])  # same forward trajectory
+    assert np.array_equal(results[0][0], results[1][0])
+    assert results[0][1] == results[1][1]
