@@ -49,12 +49,13 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel="auto", timing_slots=True):
+def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel="auto", timing_slots=True,
+              solid=None):
     """Run one storage form; return a dict of timings."""
     a, b = fields
     lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0, kernel=kernel)
     try:
-        lat.set_fields(a, b)
+        lat.set_fields(a, b, None, solid)
         lat.step(warmup)
         torch.cuda.synchronize()
         tot0, _ = lat.totals()
@@ -81,6 +82,43 @@ def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel
     mass_drift = max(abs(tot1[k] - tot0[k]) / abs(tot0[k]) for k in range(2))
     return {"event_ms": ev_ms, "wall_ms": (w1 - w0) * 1e3, "kernels": kernels, "nonfinite": nonfinite,
             "mass_drift": mass_drift}
+
+
+def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000)):
+    """Density and velocity error of the float32 and float16-shifted forms
+    against the float64 path (bitwise equal to the float64 oracle) on the
+    same initial state, at several step counts."""
+    a, b = fields
+    n = w.nodes
+    ref = {}
+    out = {}
+    for st in ("f64", "f32", "f16s"):
+        lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=st, device=0)
+        try:
+            lat.set_fields(a, b)
+            done = 0
+            rows = []
+            for s in checkpoints:
+                lat.step(s - done)
+                done = s
+                ra = torch.empty(n, dtype=torch.float64, device="cuda")
+                rb = torch.empty_like(ra)
+                u = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+                lat.moments(ra, rb, u)
+                if st == "f64":
+                    ref[s] = (ra, rb, u)
+                    continue
+                r_a, r_b, r_u = ref[s]
+                drho = torch.maximum((ra - r_a).abs(), (rb - r_b).abs())
+                du = (u - r_u).abs()
+                rows.append({"step": s, "max_drho": float(drho.max()),
+                             "rms_drho": float(torch.sqrt(0.5 * (((ra - r_a) ** 2).mean() + ((rb - r_b) ** 2).mean()))),
+                             "max_du": float(du.max()), "max_abs_u_ref": float(r_u.abs().max())})
+            if st != "f64":
+                out[st] = rows
+        finally:
+            lat.close()
+    return out
 
 
 def adjoint_run(P, torch, synth, every: int = 50):
@@ -199,6 +237,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the reduced-precision error report")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--calibrate", action="store_true",
                     help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
@@ -226,9 +265,16 @@ def main(argv=None) -> int:
     log(f"bench: workload {w.name} {w.shape} storage {w.storage}; generating inputs")
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
     fields = (a.reshape(-1), b.reshape(-1))
+    solid = None
+    solid_fraction = 0.0
+    if w.spheres:
+        centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+        solid = synth.solid_mask(w.shape, centres, w.radius).reshape(-1)
+        solid_fraction = float(solid.mean())
+        log(f"bench: {w.spheres} spheres of radius {w.radius}, solid fraction {solid_fraction:.4f}")
 
     log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
-    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields, kernel=args.kernel)
+    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields, kernel=args.kernel, solid=solid)
     ms_step = main_run["event_ms"] / args.steps
     glups = w.nodes / (ms_step * 1e-3) / 1e9
     bpl = algorithmic_bytes_per_lup(w.storage)
@@ -245,7 +291,7 @@ def main(argv=None) -> int:
                 "algorithmic_bytes_per_lup": bpl, "lups_per_launch": w.nodes}
 
     forms = {}
-    if not args.no_forms:
+    if not args.no_forms and solid is None:
         for st in ("f32", "f16s"):
             if st == w.storage:
                 continue
@@ -257,6 +303,14 @@ def main(argv=None) -> int:
                          "step_hbm_frac": round(algorithmic_bytes_per_lup(st) * g / HBM_PEAK_GBS, 4),
                          "vs_f64": round(g / glups, 3) if w.storage == "f64" else None,
                          "nonfinite": r["nonfinite"], "kernels": r["kernels"]}
+
+    accuracy = None
+    if not args.no_accuracy and solid is None and w.storage == "f64":
+        log("bench: float32 / float16-shifted error against the float64 path")
+        accuracy = accuracy_run(P, torch, w, fields)
+        for st, rows in accuracy.items():
+            if st in forms:
+                forms[st]["error_vs_f64"] = rows
 
     adjoint = None
     if not args.no_adjoint:
@@ -284,8 +338,9 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(reversed(w.shape)), "storage": w.storage,
                    "tau": list(w.tau), "G": w.G, "rho0": list(w.rho0), "noise": w.amp, "seed": w.seed,
-                   "boundary": "periodic", "solid_spheres": w.spheres},
+                   "boundary": "periodic", "solid_spheres": w.spheres, "solid_fraction": round(solid_fraction, 5)},
         "step_hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
+        "fluid_glups": round(glups * (1.0 - solid_fraction), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,

@@ -240,3 +240,47 @@ def test_record_path_equals_snapshot_path(storage):
     assert np.array_equal(results[0][2], results[1][2])  # same forward trajectory
     assert np.array_equal(results[0][0], results[1][0])
     assert results[0][1] == results[1][1]
+
+
+@pytest.mark.slow
+def test_adjoint128_gradient_against_fourth_order_differences():
+    """The 128^3, 500-step gradient workload with a float64 adjoint: dJ/drho_A(0)
+    at 16 sites and dJ/dG against fourth-order central differences of the GPU
+    float64 forward, with the objective summed exactly (math.fsum)."""
+    import math
+    torch = _torch()
+    w = synth.WORKLOADS["adjoint128_f32"]
+    shape, steps = w.shape, w.steps
+    a, b = synth.fluid_fields(shape, w.amp, w.seed)
+    target = synth.smooth_target(shape, 4)
+    _say("case adjoint128 float64 gradient vs 4th-order differences")
+    J, ga, gb, dG = _gpu_gradient(shape, a, b, target, w.tau, w.G, steps, 50, "f64")
+    tt = torch.tensor(target, device="cuda").view(-1)
+
+    def J_of(ra, G=w.G):
+        with P.Lattice(shape, tau=w.tau, G=G, storage="f64") as lat:
+            lat.set_fields(ra.ravel().copy(), b.ravel().copy())
+            lat.step(steps)
+            r = torch.empty(ra.size, dtype=torch.float64, device="cuda")
+            lat.moments(rho_a=r)
+        d = (r - tt) ** 2
+        return math.fsum(d.cpu().numpy())
+
+    def d4(f, h):
+        return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+    worst = 0.0
+    for (x, y, z) in synth.sample_sites(shape, 16, 5):
+        def f(eps):
+            ap = a.copy()
+            ap[z, y, x] += eps
+            return J_of(ap)
+        fd1, fd2 = d4(f, 2e-5), d4(f, 4e-5)
+        rel = abs(fd1 - ga[z, y, x]) / abs(fd1)
+        worst = max(worst, rel)
+        _say(f"  site {(int(x), int(y), int(z))}: fd {fd1:.10e} (h=4e-5: {fd2:.10e}) adjoint {ga[z, y, x]:.10e} rel {rel:.2e}")
+        assert rel <= 1e-6
+    fdG = d4(lambda eps: J_of(a, w.G + eps), 1e-5)
+    relG = abs(fdG - dG) / abs(fdG)
+    _say(f"  G: fd {fdG:.10e} adjoint {dG:.10e} rel {relG:.2e}; worst site {worst:.2e}")
+    assert relG <= 1e-6

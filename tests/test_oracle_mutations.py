@@ -1,0 +1,96 @@
+"""Planted mistakes in the oracle must make a pin fail (no GPU).
+
+Each case copies an oracle source file with one plausible error planted (a
+dropped term, a flipped sign, a wrong index or weight, a shift the wrong
+way), loads it in place of the real module in a fresh interpreter, and runs
+the pin tests against it.  The case passes only if some pin fails.
+"""
+
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TESTS = os.path.join(ROOT, "tests")
+
+FORWARD = [
+    ("feq 4.5 -> 4.0", "+ 4.5 * cu * cu)", "+ 4.0 * cu * cu)"),
+    ("feq drops -1.5 v.v", " - 1.5 * vv)", ")"),
+    ("force sign flipped", "v = [up[a] - a_k * S[k][a] for a in range(3)]",
+     "v = [up[a] + a_k * S[k][a] for a in range(3)]"),
+    ("stencil uses own component", "S = [sc_sum(psi[1]), sc_sum(psi[0])]\n    den",
+     "S = [sc_sum(psi[0]), sc_sum(psi[1])]\n    den"),
+    ("stencil neighbour reversed", "t = W[i] * _neighbour(psi_other, C[i])", "t = W[i] * _shift(psi_other, C[i])"),
+    ("common velocity not tau-weighted",
+     "up = tuple((om[0] * m[0][a] + om[1] * m[1][a]) / den for a in range(3))",
+     "up = tuple((m[0][a] + m[1][a]) / (rho[0] + rho[1]) for a in range(3))"),
+    ("streaming the wrong way", "pulled = _shift(fs[:, i], C[i])", "pulled = _neighbour(fs[:, i], C[i])"),
+    ("bounce-back keeps the index", "pulled = np.where(src_solid, fs[:, OPP[i]], pulled)",
+     "pulled = np.where(src_solid, fs[:, i], pulled)"),
+    ("psi = rho", "return psi_ref * (1.0 - exp_cw(-(rho / psi_ref)))", "return rho * 1.0"),
+    ("exp coefficient off", "EXP_COEF = [1.0 / math.factorial(k) for k in range(EXP_DEGREE + 1)]",
+     "EXP_COEF = [1.0 / math.factorial(k) for k in range(EXP_DEGREE + 1)]; EXP_COEF[5] *= 1.001"),
+    ("diagonal weight 1/36 -> 1/30", "[1.0 / 36.0] * 12", "[1.0 / 30.0] * 12"),
+    ("relaxation uses omega of the other component", "fs[k] = omc * f[k] + om[k] * feq",
+     "fs[k] = omc * f[k] + om[1 - k] * feq"),
+]
+
+ADJOINT = [
+    ("drops the psi-stencil term", " - dpsi[k] * T", ""),
+    ("common-velocity term sign", "- om[k] * (U * up).sum(axis=0) / D", "+ om[k] * (U * up).sum(axis=0) / D"),
+    ("drops the g' term", " - VS * p.tau[k] * p.G * dg[k]", ""),
+    ("stencil transpose shifted the wrong way", "O._shift(Wk[kb], C[j])", "O._neighbour(Wk[kb], C[j])"),
+    ("bounce-back not transposed", "a[:, i] = np.where(dst_solid, lam_next[:, O.OPP[i]], a[:, i])", "pass"),
+    ("stencil transpose uses own component", "O._shift(Wk[kb], C[j])", "O._shift(Wk[k], C[j])"),
+]
+
+RUNNER = r"""
+import importlib.util, sys
+sys.path.insert(0, {root!r})
+import oracle
+spec = importlib.util.spec_from_file_location({modname!r}, {path!r})
+m = importlib.util.module_from_spec(spec)
+m.__package__ = "oracle"
+sys.modules[{modname!r}] = m
+spec.loader.exec_module(m)
+setattr(oracle, {attr!r}, m)
+import pytest
+sys.exit(pytest.main(["-q", "-x", "-p", "no:cacheprovider", "-m", "not slow", *{tests!r}]))
+"""
+
+
+def _run_mutant(src_file, modname, attr, old, new, tests):
+    src = open(os.path.join(ROOT, "oracle", src_file)).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, src_file)
+        with open(path, "w") as fh:
+            fh.write(src.replace(old, new, 1))
+        code = RUNNER.format(root=ROOT, modname=modname, path=path, attr=attr, tests=tests)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=600)
+    return r.returncode
+
+
+@pytest.mark.parametrize("name,old,new", FORWARD, ids=[m[0] for m in FORWARD])
+def test_forward_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_units.py"), os.path.join(TESTS, "test_oracle_physics.py")]
+    rc = _run_mutant("lb_oracle.py", "oracle.lb_oracle", "lb_oracle", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
+@pytest.mark.parametrize("name,old,new", ADJOINT, ids=[m[0] for m in ADJOINT])
+def test_adjoint_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
+    rc = _run_mutant("lb_adjoint.py", "oracle.lb_adjoint", "lb_adjoint", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
+def test_unmutated_oracle_passes_through_the_same_runner():
+    # the runner itself must not fail on the real oracle
+    tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
+    rc = _run_mutant("lb_adjoint.py", "oracle.lb_adjoint", "lb_adjoint", "import numpy as np", "import numpy as np",
+                     tests)
+    assert rc == 0
