@@ -84,15 +84,75 @@ def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel
             "mass_drift": mass_drift}
 
 
-def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000)):
-    """Density and velocity error of the float32 and float16-shifted forms
-    against the float64 path (bitwise equal to the float64 oracle) on the
-    same initial state, at several step counts."""
+def _moments(torch, lat, n):
+    ra = torch.empty(n, dtype=torch.float64, device="cuda")
+    rb = torch.empty_like(ra)
+    u = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    lat.moments(ra, rb, u)
+    return ra, rb, u
+
+
+def _error_row(torch, got, ref, **key):
+    ra, rb, u = got
+    r_a, r_b, r_u = ref
+    drho = torch.maximum((ra - r_a).abs(), (rb - r_b).abs())
+    return dict(key, max_drho=float(drho.max()),
+                rms_drho=float(torch.sqrt(0.5 * (((ra - r_a) ** 2).mean() + ((rb - r_b) ** 2).mean()))),
+                max_du=float((u - r_u).abs().max()), max_abs_u_ref=float(r_u.abs().max()))
+
+
+def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000), restart=(1, 10)):
+    """Error of the float32 and float16-shifted forms against the float64 path
+    (bitwise equal to the float64 oracle), measured three ways:
+
+    * trajectory: the same initial state run by each form, compared at several
+      step counts;
+    * sensitivity: the float64 path itself, started from rho_A nudged by one
+      ulp at every node, compared with the unperturbed float64 run.  A quench
+      at G = 3.5 amplifies any difference exponentially, so once this floor
+      reaches a form's trajectory error, that error measures the flow's
+      sensitivity, not the storage;
+    * restart: the float64 state after the last checkpoint loaded into each
+      form (one rounding to its storage) and advanced a few steps, compared
+      with float64 advanced the same steps -- the storage error per step in
+      the demixed state, without the amplification."""
+    import numpy as np
     a, b = fields
     n = w.nodes
-    ref = {}
-    out = {}
-    for st in ("f64", "f32", "f16s"):
+    last = checkpoints[-1]
+    ref, ref_restart = {}, {}
+    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage="f64", device=0)
+    try:
+        lat.set_fields(a, b)
+        done = 0
+        for s in checkpoints:
+            lat.step(s - done)
+            done = s
+            ref[s] = _moments(torch, lat, n)
+        pop = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(pop)
+        done = 0
+        for s in restart:
+            lat.step(s - done)
+            done = s
+            ref_restart[s] = _moments(torch, lat, n)
+    finally:
+        lat.close()
+
+    sens = []
+    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage="f64", device=0)
+    try:
+        lat.set_fields(np.nextafter(a, np.inf), b)
+        done = 0
+        for s in checkpoints:
+            lat.step(s - done)
+            done = s
+            sens.append(_error_row(torch, _moments(torch, lat, n), ref[s], step=s))
+    finally:
+        lat.close()
+
+    out = {"f64_one_ulp": sens}
+    for st in ("f32", "f16s"):
         lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=st, device=0)
         try:
             lat.set_fields(a, b)
@@ -101,23 +161,18 @@ def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000)):
             for s in checkpoints:
                 lat.step(s - done)
                 done = s
-                ra = torch.empty(n, dtype=torch.float64, device="cuda")
-                rb = torch.empty_like(ra)
-                u = torch.empty(3 * n, dtype=torch.float64, device="cuda")
-                lat.moments(ra, rb, u)
-                if st == "f64":
-                    ref[s] = (ra, rb, u)
-                    continue
-                r_a, r_b, r_u = ref[s]
-                drho = torch.maximum((ra - r_a).abs(), (rb - r_b).abs())
-                du = (u - r_u).abs()
-                rows.append({"step": s, "max_drho": float(drho.max()),
-                             "rms_drho": float(torch.sqrt(0.5 * (((ra - r_a) ** 2).mean() + ((rb - r_b) ** 2).mean()))),
-                             "max_du": float(du.max()), "max_abs_u_ref": float(r_u.abs().max())})
-            if st != "f64":
-                out[st] = rows
+                rows.append(_error_row(torch, _moments(torch, lat, n), ref[s], step=s))
+            lat.set_populations(pop)
+            done = 0
+            rrows = []
+            for s in restart:
+                lat.step(s - done)
+                done = s
+                rrows.append(_error_row(torch, _moments(torch, lat, n), ref_restart[s], restart_step=last, steps=s))
+            out[st] = {"trajectory": rows, "restart": rrows}
         finally:
             lat.close()
+    del pop
     return out
 
 
@@ -238,7 +293,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reduced-precision error report")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass", "fused_staged"])
     ap.add_argument("--calibrate", action="store_true",
                     help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
     args = ap.parse_args(argv)
@@ -308,9 +363,10 @@ def main(argv=None) -> int:
     if not args.no_accuracy and solid is None and w.storage == "f64":
         log("bench: float32 / float16-shifted error against the float64 path")
         accuracy = accuracy_run(P, torch, w, fields)
-        for st, rows in accuracy.items():
+        for st in ("f32", "f16s"):
             if st in forms:
-                forms[st]["error_vs_f64"] = rows
+                forms[st]["error_vs_f64"] = accuracy[st]["trajectory"]
+                forms[st]["error_vs_f64_restart"] = accuracy[st]["restart"]
 
     adjoint = None
     if not args.no_adjoint:
@@ -344,6 +400,7 @@ def main(argv=None) -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "f64_one_ulp_sensitivity": None if accuracy is None else accuracy["f64_one_ulp"],
         "adjoint_forward_ratio": None if adjoint is None else adjoint["ratio"],
         "adjoint": adjoint,
         "mass_drift": main_run["mass_drift"],
