@@ -143,13 +143,22 @@ lb_status lb_timing_read(lb_ctx* ctx, int32_t slot, double* total_ms, int64_t* l
 int32_t lb_timing_slots(void);
 const char* lb_timing_name(int32_t slot);
 
-/* Step implementation.  LB_KERNEL_FUSED (the default; LB_KERNEL_AUTO picks
- * it) reads and writes every population once per step: one kernel marches
- * z-columns and keeps the pseudopotential of three planes in LDS.
- * LB_KERNEL_TWO_PASS computes the pseudopotential field in a first kernel
- * and collides and streams in a second.  Both give bitwise identical results
- * for LB_F64.  Errors: LB_EINVAL (unknown value). */
-typedef enum { LB_KERNEL_AUTO = 0, LB_KERNEL_FUSED = 1, LB_KERNEL_TWO_PASS = 2 } lb_kernel;
+/* Step implementation.  LB_KERNEL_FUSED reads and writes every population
+ * once per step: one kernel marches z-columns and keeps the pseudopotential
+ * of three planes in LDS.  LB_KERNEL_FUSED_STAGED (the default;
+ * LB_KERNEL_AUTO picks it) is the same march for LB_F64 with nx a multiple
+ * of 32, where the populations of the plane two ahead are copied into LDS by
+ * direct-to-LDS loads while the current plane is collided; other storages
+ * and shapes run LB_KERNEL_FUSED.  LB_KERNEL_TWO_PASS computes the
+ * pseudopotential field in a first kernel and collides and streams in a
+ * second.  All give bitwise identical results for LB_F64.
+ * Errors: LB_EINVAL (unknown value). */
+typedef enum {
+  LB_KERNEL_AUTO = 0,
+  LB_KERNEL_FUSED = 1,
+  LB_KERNEL_TWO_PASS = 2,
+  LB_KERNEL_FUSED_STAGED = 3
+} lb_kernel;
 lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel);
 
 /* Change the Shan-Chen coupling G of later steps (and adjoint steps).

@@ -71,7 +71,7 @@ struct lb_ctx {
   double* adj_partial = nullptr;      // per-block dJ/dG
   double* adj_dG = nullptr;           // running dJ/dG
   bool adj_ready = false;
-  int kernel = LB_KERNEL_FUSED;
+  int kernel = LB_KERNEL_FUSED_STAGED;  // LB_KERNEL_AUTO
   FusedTiling tiling{};
   int64_t bytes = 0;
 };
@@ -181,34 +181,41 @@ const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->ma
 // ---------------------------------------------------------------------------
 // Typed implementations
 // ---------------------------------------------------------------------------
-// One fused step from fin to fout.  float64: component-pair waves without
-// register prefetch (two planes of float64 populations fill the register
-// budget); float32 arithmetic: single-component waves with a prefetch depth
-// of three planes.  With rec != nullptr the kernel also writes the moment
-// record of the pre-collision state for the adjoint.
+// One fused step from fin to fout.  float64: component-pair waves, either
+// without prefetch or (LB_KERNEL_FUSED_STAGED, nx a multiple of 32) with the
+// plane two ahead staged into LDS by direct-to-LDS loads; float32
+// arithmetic: single-component waves with a register prefetch depth of three
+// planes.  With rec != nullptr the kernel also writes the moment record of
+// the pre-collision state for the adjoint.
+bool staged_fits(const lb_ctx* ctx) { return ctx->p.storage == LB_F64 && ctx->p.nx % kFusedTX == 0; }
+
+template <int ST, bool SOLID, bool RECORD>
+void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
+                     typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
+  const FusedTiling t = ctx->tiling;
+  const uint8_t* m = SOLID ? ctx->mask : nullptr;
+  const dim3 grid(t.total), block(64 * kFusedTY);
+  if constexpr (ST == ST_F64) {
+    if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_fits(ctx))
+      k_fused_pair<ST, SOLID, kFusedTY, RECORD, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+    else
+      k_fused_pair<ST, SOLID, kFusedTY, RECORD, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+  } else {
+    k_fused<ST, SOLID, kFusedTY, 3, RECORD><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+  }
+}
+
 template <int ST>
 lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
                        typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
-  const FusedTiling t = ctx->tiling;
-  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
-  const dim3 grid(t.total), block(64 * kFusedTY);
+  const bool solid = ctx->has_solid;
   return launch(ctx, SLOT_FUSED, [&] {
-    if constexpr (ST == ST_F64) {
-      if (m) {
-        if (rec) k_fused_pair<ST, true, kFusedTY, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-        else k_fused_pair<ST, true, kFusedTY, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-      } else {
-        if (rec) k_fused_pair<ST, false, kFusedTY, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-        else k_fused_pair<ST, false, kFusedTY, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-      }
+    if (solid) {
+      if (rec) launch_fused_as<ST, true, true>(ctx, fin, fout, rec);
+      else launch_fused_as<ST, true, false>(ctx, fin, fout, rec);
     } else {
-      if (m) {
-        if (rec) k_fused<ST, true, kFusedTY, 3, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-        else k_fused<ST, true, kFusedTY, 3, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-      } else {
-        if (rec) k_fused<ST, false, kFusedTY, 3, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-        else k_fused<ST, false, kFusedTY, 3, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-      }
+      if (rec) launch_fused_as<ST, false, true>(ctx, fin, fout, rec);
+      else launch_fused_as<ST, false, false>(ctx, fin, fout, rec);
     }
   });
 }
@@ -226,12 +233,15 @@ lb_status fused_step_impl(lb_ctx* ctx, int n) {
   return LB_OK;
 }
 
-// The fused kernel addresses a population plane with 32-bit byte offsets.
+// The fused kernels address a population plane with 32-bit byte offsets.
 bool fused_fits(const lb_ctx* ctx) { return static_cast<double>(ctx->g.N) * ctx->elem < 4294967296.0; }
+bool use_fused(const lb_ctx* ctx) {
+  return (ctx->kernel == LB_KERNEL_FUSED || ctx->kernel == LB_KERNEL_FUSED_STAGED) && fused_fits(ctx);
+}
 
 template <int ST>
 lb_status step_impl(lb_ctx* ctx, int n) {
-  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) return fused_step_impl<ST>(ctx, n);
+  if (use_fused(ctx)) return fused_step_impl<ST>(ctx, n);
   using store = typename StorageTraits<ST>::store_t;
   using real = typename StorageTraits<ST>::real;
   const int nb = blocks_for(ctx->g.N);
@@ -327,7 +337,7 @@ lb_status step_between_impl(lb_ctx* ctx, const void* fin, void* fout) {
   using real = typename StorageTraits<ST>::real;
   const store* a = static_cast<const store*>(fin);
   store* b = static_cast<store*>(fout);
-  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) return launch_fused<ST>(ctx, a, b, nullptr);
+  if (use_fused(ctx)) return launch_fused<ST>(ctx, a, b, nullptr);
   const int nb = blocks_for(ctx->g.N);
   real* psi = static_cast<real*>(ctx->psi);
   const uint8_t* m = mask_or_null(ctx);
@@ -421,7 +431,7 @@ lb_status step_record_impl(lb_ctx* ctx, void* record) {
   store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
   real* rec = static_cast<real*>(record);
   lb_status st;
-  if (ctx->kernel == LB_KERNEL_FUSED && fused_fits(ctx)) {
+  if (use_fused(ctx)) {
     st = launch_fused<ST>(ctx, fin, fout, rec);
   } else {
     st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
@@ -621,8 +631,8 @@ lb_status lb_set_stream(lb_ctx* ctx, void* stream) {
 
 lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel) {
   if (ctx == nullptr) return LB_EINVAL;
-  if (kernel == LB_KERNEL_AUTO) kernel = LB_KERNEL_FUSED;
-  if (kernel != LB_KERNEL_FUSED && kernel != LB_KERNEL_TWO_PASS) return LB_EINVAL;
+  if (kernel == LB_KERNEL_AUTO) kernel = LB_KERNEL_FUSED_STAGED;  // runs as LB_KERNEL_FUSED where it does not apply
+  if (kernel != LB_KERNEL_FUSED && kernel != LB_KERNEL_TWO_PASS && kernel != LB_KERNEL_FUSED_STAGED) return LB_EINVAL;
   ctx->kernel = kernel;
   return LB_OK;
 }

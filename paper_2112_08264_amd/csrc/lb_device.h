@@ -182,6 +182,30 @@ __device__ __forceinline__ real cdot(int i, real vx, real vy, real vz) {
 }
 
 // ---------------------------------------------------------------------------
+// float arithmetic only (float32 and float16-shifted storage, which are not
+// bound to the float64 operation order): BGK relaxation of one component's
+// 19 populations towards f^eq(rho, v).  Opposite directions i, i + 1 share
+// the even part of f^eq, w rho (1 - 1.5 v.v + 4.5 (c.v)^2), and differ in
+// the sign of its odd part, 3 w rho c.v; products are fused.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void relax_f32(const float (&f)[Q], float (&fs)[Q], float rho, float vx, float vy,
+                                          float vz, float om, float omc) {
+  const float vv = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+  const float a0 = fmaf(-1.5f, vv, 1.0f);
+  const float orho = om * rho;
+  fs[0] = fmaf(omc, f[0], (orho * weight<float>(0)) * a0);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {  // OPP[i] == i + 1
+    const float cu = cdot<float>(i, vx, vy, vz);
+    const float e = orho * weight<float>(i);
+    const float even = e * fmaf(4.5f * cu, cu, a0);
+    const float odd = (3.0f * e) * cu;
+    fs[i] = fmaf(omc, f[i], even) + odd;
+    fs[i + 1] = fmaf(omc, f[i + 1], even) - odd;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Velocity-shifted BGK collision of both components at one node, in place.
 //   f        : the 2 x 19 pre-collision populations (overwritten by f*)
 //   psi_nb   : psi_A and psi_B at x + c_i, i = 1..18 (index 0 unused)

@@ -40,6 +40,17 @@ namespace lbd {
 constexpr int kFusedTX = 32;
 constexpr int kXCDs = 8;
 
+// Workgroup barrier that orders LDS accesses only.  The waves of a fused
+// workgroup exchange data through LDS alone (the kernels never read what
+// they write to global memory), so global stores -- and register loads
+// issued ahead -- may stay in flight across it.  __syncthreads() would wait
+// for every outstanding vector memory operation of the wave at each barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct FusedTiling {
   int tiles_x, tiles_y;  // tile counts along x and y
   int chunk;             // planes per z-chunk
@@ -68,6 +79,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
   constexpr int NS = D + 2;                // ring slots: planes z - 1 .. z + D
   constexpr int NX = D + 1;                // exchange slots: planes z .. z + D
   static_assert(D >= 2, "psi of plane z + 1 must be ready before plane z is collided");
+  static_assert(sizeof(real) == 4, "float arithmetic only; float64 storage runs k_fused_pair");
   static_assert(TY % 2 == 0 && TY >= 6, "three row-pairs per component carry the halo");
   __shared__ real ring[NS][2][RY][RX];
   __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
@@ -190,30 +202,34 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
     if constexpr (SOLID) here_solid = ring_solid[s0][ly + 1][lx + 1] != 0;
     const real rhoA = xch[par][0][0][ly][lx], rhoB = xch[par][1][0][ly][lx];
     const real rho_k = k == 0 ? rhoA : rhoB;
-    const real den = omA * rhoA + omB * rhoB;
+    // float arithmetic: one reciprocal and fused products (this kernel
+    // serves float32 and float16-shifted storage only)
+    const real inv_den = real(1) / fmaf(omA, rhoA, omB * rhoB);
     real up[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) up[a] = (omA * xch[par][0][1 + a][ly][lx] + omB * xch[par][1][1 + a][ly][lx]) / den;
-    real S[3] = {real(0), real(0), real(0)};
+    for (int a = 0; a < 3; ++a) up[a] = fmaf(omA, xch[par][0][1 + a][ly][lx], omB * xch[par][1][1 + a][ly][lx]) * inv_den;
+    // S = sum_i w_i psi(x + c_i) c_i, by weight class: sum the unit-weight
+    // differences first, then scale once per class
+    real S1[3] = {real(0), real(0), real(0)}, S2[3] = {real(0), real(0), real(0)};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-      const real tt = weight<real>(i) * ring[si][1 - k][ly + 1 + CY[i]][lx + 1 + CX[i]];
-      if (CX[i] == 1) S[0] = S[0] + tt;
-      if (CX[i] == -1) S[0] = S[0] - tt;
-      if (CY[i] == 1) S[1] = S[1] + tt;
-      if (CY[i] == -1) S[1] = S[1] - tt;
-      if (CZ[i] == 1) S[2] = S[2] + tt;
-      if (CZ[i] == -1) S[2] = S[2] - tt;
+      const real p = ring[si][1 - k][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      real (&Sw)[3] = i < 7 ? S1 : S2;
+      if (CX[i] == 1) Sw[0] = Sw[0] + p;
+      if (CX[i] == -1) Sw[0] = Sw[0] - p;
+      if (CY[i] == 1) Sw[1] = Sw[1] + p;
+      if (CY[i] == -1) Sw[1] = Sw[1] - p;
+      if (CZ[i] == 1) Sw[2] = Sw[2] + p;
+      if (CZ[i] == -1) Sw[2] = Sw[2] - p;
     }
     const real psi_k = ring[s0][k][ly + 1][lx + 1];
     const real ratio = rho_k == real(0) ? real(1) : psi_k / rho_k;
     const real ak = tgk * ratio;
-    const real vx = up[0] - ak * S[0];
-    const real vy = up[1] - ak * S[1];
-    const real vz = up[2] - ak * S[2];
-    const real vv = (vx * vx + vy * vy) + vz * vz;
-    const real t15 = real(1.5) * vv;
+    real v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = fmaf(-ak, fmaf(weight<real>(1), S1[a], weight<real>(7) * S2[a]), up[a]);
+    const real vx = v[0], vy = v[1], vz = v[2];
     if constexpr (RECORD) {
       if (active) {
         const size_t node = row + plane_n * (uint32_t)z;
@@ -227,11 +243,11 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
     if (active && !here_solid) {
       const uint32_t Z[3] = {plane_n * (uint32_t)wrapz(z - 1), plane_n * (uint32_t)z, plane_n * (uint32_t)wrapz(z + 1)};
       const uint32_t here = row + Z[1];
+      real fs_all[Q];
+      relax_f32(hold[0], fs_all, rho_k, vx, vy, vz, omk, omck);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const real cu = cdot<real>(i, vx, vy, vz);
-        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
-        const real fs = omck * hold[0][i] + omk * feq;
+        const real fs = fs_all[i];
         uint32_t dn = X[CX[i] + 1] + Y[CY[i] + 1] + Z[CZ[i] + 1];
         int di = i;
         if constexpr (SOLID) {
@@ -249,7 +265,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
 
     // ---- C: psi and exchange of plane z + D ----
     if (more) publish(z + D, pre, hpre);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
 #pragma unroll
@@ -264,11 +280,26 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
 // TX = 32 nodes for both components: lanes 0..31 carry component A, lanes
 // 32..63 component B of the same nodes, and the partner lane (lane ^ 32)
 // supplies the other component's density and momentum by a lane shuffle.
-// No register prefetch: the plane z + 1 loads are consumed in the same
-// iteration, which keeps the float64 register budget (two planes of 19
-// populations) within 256 VGPRs without spilling.  Ring of three planes.
+// Ring of three psi planes.
+//
+// STAGED = false: no prefetch.  The plane z + 1 loads go to registers and
+// are consumed in the same iteration, which keeps the float64 register
+// budget (two planes of 19 populations) within 256 VGPRs without spilling,
+// but leaves their latency exposed.
+//
+// STAGED = true (float64 storage, nx a multiple of 32, TY = 8): the
+// populations of plane z + 2 -- the tile's rows -1 .. TY and its two side
+// columns, both components -- are copied from HBM straight into an LDS
+// stage by direct-to-LDS loads (global_load_lds, which bypass the
+// registers), issued before plane z is collided and waited for after its
+// stores.  Their latency hides behind a whole collision without costing a
+// register.  After the wait, psi of plane z + 2 is formed from the stage and
+// the plane's interior populations move into registers for its own
+// collision two iterations later.  Stage: 38 population planes x (10 rows x
+// 32 nodes + 20 side nodes) float64 = 103,360 bytes, so one workgroup per
+// compute unit.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID, int TY, bool RECORD>
+template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED>
 __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                         store_t<ST>* __restrict__ fout,
                                                         const uint8_t* __restrict__ mask, Geometry g,
@@ -277,8 +308,15 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
   constexpr int TX = kFusedTX;
   constexpr int RX = TX + 2, RY = TY + 2;
   static_assert(2 * (2 * RX + 2 * TY) <= 64 * TY, "too few lanes for the halo tasks");
+  static_assert(!STAGED || (sizeof(store_t<ST>) == 8 && TY % 2 == 0 && 4 * (TY + 2) <= 64),
+                "the stage layout assumes float64, and one wave covers the side columns");
+  constexpr int NQ = ((TY + 2) * 16 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
+  constexpr int KI = 2 * Q;                      // population planes of both components
+  constexpr int ST_ROWS = KI * RY * TX;          // [ki][row -1 .. TY][x] block
+  constexpr int ST_SIDE = KI * 2 * RY;           // [ki][left rows -1 .. TY, right rows -1 .. TY]
+  __shared__ real stage[STAGED ? ST_ROWS + ST_SIDE : 1];
 
   const int w = fused_work_item(blockIdx.x, t.total);
   const int chunk = w / (t.tiles_x * t.tiles_y);
@@ -316,6 +354,57 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
 
   auto wrapz = [&](int z) { return z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z); };
 
+  // ---- direct-to-LDS staging (STAGED only) ----
+  // Byte offsets within one z-plane of a population plane.  Rows: chunk
+  // c = 64 q + lane (c < 160) covers row c / 16 - 1 of the tile and x =
+  // 2 (c % 16), 2 (c % 16) + 1 (16 bytes).  Sides: lane < 40 covers one half
+  // of the float64 at side node lane / 2 (left column for < 10, right
+  // column after, rows -1 .. TY).
+  uint32_t voff16[NQ] = {}, voff4 = 0;
+  bool on16[NQ] = {}, on4 = false;
+  int ibase = 0, hbase = 0;  // stage index of value 0 of this lane's interior node and halo node
+  bool hrows = false;        // halo node in a stage row (else in a side column)
+  if constexpr (STAGED) {
+    auto wrapy = [&](int y) { return ((y % g.ny) + g.ny) % g.ny; };  // y may be off by more than ny when ny < TY
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int cq = 64 * q + lane;
+      on16[q] = cq < RY * 16;
+      const int r = cq >> 4, xp = cq & 15;
+      voff16[q] = (uint32_t)(((uint32_t)(tx0 + 2 * xp) + (uint32_t)g.nx * (uint32_t)wrapy(ty0 + r - 1)) * 8u);
+    }
+    on4 = lane < 4 * RY;
+    {
+      const int sn = lane >> 1, r = sn % RY;
+      const int sx = sn < RY ? (tx0 == 0 ? g.nx - 1 : tx0 - 1) : (tx0 + TX == g.nx ? 0 : tx0 + TX);
+      voff4 = (uint32_t)(((uint32_t)sx + (uint32_t)g.nx * (uint32_t)wrapy(ty0 + r - 1)) * 8u + 4u * (uint32_t)(lane & 1));
+    }
+    ibase = (k * Q * RY + ly + 1) * TX + lx;
+    hrows = hx >= 0 && hx < TX;
+    hbase = hrows ? (hk * Q * RY + hy + 1) * TX + hx : ST_ROWS + hk * Q * 2 * RY + (hx < 0 ? 0 : RY) + hy + 1;
+  }
+  // Issue the loads of plane zz into the stage.  Wave w copies population
+  // planes ki = w, w + 8, ... (uniform per wave).
+  auto stage_issue = [&](int zz) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef __attribute__((address_space(1))) void glb_void;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const char* zbase = reinterpret_cast<const char*>(fin) + (size_t)plane_n * (size_t)zz * 8u;
+#pragma unroll
+    for (int m = 0; m < (KI + TY - 1) / TY; ++m) {
+      const int ki = wv + TY * m;
+      if (ki < KI) {
+        const char* base = zbase + (size_t)ki * (size_t)g.Npad * 8u;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (on16[q])
+            __builtin_amdgcn_global_load_lds((glb_void*)(base + voff16[q]),
+                                             (lds_void*)(&stage[(ki * RY + 4 * q) * TX]), 16, 0, 0);
+        if (on4) __builtin_amdgcn_global_load_lds((glb_void*)(base + voff4), (lds_void*)(&stage[ST_ROWS + ki * 2 * RY]), 4, 0, 0);
+      }
+    }
+  };
+
   auto psi_of = [&](long long n, long long kp, int kk, bool solid, real (&v)[Q]) -> real {
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = decode<ST>(fin[kp + (long long)i * g.Npad + n], c.shift[kk][i]);
@@ -348,6 +437,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
   real cur[Q], nxt[Q];
   fill(0, wrapz(z0 - 1), nxt);  // populations of plane z0 - 1 are not needed
   fill(1, z0, cur);
+  if constexpr (STAGED) fill(2, wrapz(z0 + 1), nxt);
   __syncthreads();
 
   const real omk = coef_om<real>(c, k), omck = coef_omc<real>(c, k), tgk = coef_tg<real>(c, k);
@@ -356,8 +446,23 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
   for (int j = 0; j < zlen; ++j) {
     const int z = z0 + j;
     const int sm = j % 3, s0 = (j + 1) % 3, sp = (j + 2) % 3;  // ring slots of planes z-1, z, z+1
-    fill(sp, wrapz(z + 1), nxt);
-    __syncthreads();
+    // STAGED: plane z + 2 is loaded while plane z is collided; its psi is
+    // needed unless z + 1 is the chunk's far neighbour plane.
+    const bool more = j + 2 <= zlen;
+    bool n_solid = false, nh_solid = false;
+    if constexpr (STAGED) {
+      if (more) {
+        const int zz = (z + 2) % g.nz;
+        stage_issue(zz);
+        if constexpr (SOLID) {
+          n_solid = mask[row + plane_n * zz] != 0;
+          if (has_halo) nh_solid = mask[hrow + plane_n * zz] != 0;
+        }
+      }
+    } else {
+      fill(sp, wrapz(z + 1), nxt);
+      __syncthreads();
+    }
 
     bool here_solid = false;
     if constexpr (SOLID) here_solid = ring_solid[s0][ly + 1][lx + 1] != 0;
@@ -405,7 +510,12 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
       }
     }
 
-    if (active && !here_solid) {
+    // Post-collision populations.  STAGED keeps them in `cur` (and the
+    // bounce-back directions in a bit mask, since ring slot sm is refilled
+    // before they are stored) and stores them after the stage wait, so that
+    // the stores drain during the next collision instead of delaying the wait.
+    uint32_t bounced = 0;
+    auto push = [&](const real (&fs)[Q], uint32_t bb) {
       const int zm = wrapz(z - 1), zp = wrapz(z + 1);
       const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx == g.nx - 1 ? 0 : gx + 1;
       const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
@@ -415,23 +525,73 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
       const long long here = row + plane_n * z;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const real cu = cdot<real>(i, vx, vy, vz);
-        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
-        const real fs = omck * cur[i] + omk * feq;
         long long dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
                         (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
+        if constexpr (SOLID)
+          if ((bb >> i) & 1u) dst = kplane + (long long)OPP[i] * g.Npad + here;
+        fout[dst] = encode<ST>(fs[i], c.shift[k][i]);
+      }
+    };
+    if (active && !here_solid) {
+      real fs[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real cu = cdot<real>(i, vx, vy, vz);
+        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+        fs[i] = omck * cur[i] + omk * feq;
         if constexpr (SOLID) {
           if (i != 0) {
             const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-            if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) dst = kplane + (long long)OPP[i] * g.Npad + here;
+            if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) bounced |= 1u << i;
           }
         }
-        fout[dst] = encode<ST>(fs, c.shift[k][i]);
+      }
+      if constexpr (STAGED) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = fs[i];
+      } else {
+        push(fs, bounced);
       }
     }
+    if constexpr (STAGED) {
+      const bool store = active && !here_solid;
+      if (more) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stage loads have landed
+        lds_barrier();                        // ... and every other wave's; ring slot sm is free
+        if (has_halo) {
+          // constant strides, so that every read is one base register plus an immediate offset
+          real h[Q];
+          if (hrows) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
-    __syncthreads();
+            for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * RY * TX];
+          } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * 2 * RY];
+          }
+          ring[sm][hk][hy + 1][hx + 1] = (SOLID && nh_solid) ? real(0) : pseudopotential(density<real>(h), coef_ref<real>(c));
+          if constexpr (SOLID) if (hk == 0) ring_solid[sm][hy + 1][hx + 1] = nh_solid;
+        }
+        if (store) push(cur, bounced);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          cur[i] = nxt[i];
+          nxt[i] = stage[ibase + i * RY * TX];
+        }
+        ring[sm][k][ly + 1][lx + 1] = (SOLID && n_solid) ? real(0) : pseudopotential(density<real>(nxt), coef_ref<real>(c));
+        if constexpr (SOLID) if (k == 0) ring_solid[sm][ly + 1][lx + 1] = n_solid;
+      } else {
+        if (store) push(cur, bounced);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+      }
+      lds_barrier();  // psi of z + 2 visible; the stage may be refilled
+    } else {
+      // A full barrier here measured faster than an LDS-only one: the wave
+      // then issues its next loads only after its stores have drained.
+#pragma unroll
+      for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+      __syncthreads();
+    }
   }
 }
 

@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liblb.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
 LB_F64, LB_F32, LB_F16_SHIFTED = 0, 1, 2
-LB_KERNEL_AUTO, LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1, 2
-KERNELS = {"auto": LB_KERNEL_AUTO, "fused": LB_KERNEL_FUSED, "two_pass": LB_KERNEL_TWO_PASS}
+LB_KERNEL_AUTO, LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS, LB_KERNEL_FUSED_STAGED = 0, 1, 2, 3
+KERNELS = {"auto": LB_KERNEL_AUTO, "fused": LB_KERNEL_FUSED, "two_pass": LB_KERNEL_TWO_PASS,
+           "fused_staged": LB_KERNEL_FUSED_STAGED}
 STORAGE = {"f64": LB_F64, "f32": LB_F32, "f16s": LB_F16_SHIFTED}
 Q = 19
 
