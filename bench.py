@@ -282,6 +282,65 @@ def traffic_from_profile(kernel: str, workload: str, lups_per_launch: int):
     return ent.get("bytes_per_launch")
 
 
+def write_traffic(prof_dir: str, workload: str = "spinodal256_f64", kernel_key: str = "fused") -> dict:
+    """Turn two rocprofv3 counter runs of the bench (FETCH_SIZE, then
+    WRITE_SIZE, each in its own directory pmc_<COUNTER>/) and two of
+    ``--calibrate`` (cal_<COUNTER>/) into HBM bytes per launch of the
+    dominant fused kernel, scaled by what the counters read for the 2 GiB
+    copy, and record them in profiles/traffic.json under the current kernel
+    source digest."""
+    import csv
+
+    def rows(sub, prefix):
+        path = os.path.join(prof_dir, sub, f"{prefix}_counter_collection.csv")
+        with open(path, newline="") as fh:
+            return list(csv.DictReader(fh))
+
+    def per_kernel(rs):
+        acc = {}
+        for r in rs:
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    copy_bytes = 2 << 30
+    out = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = per_kernel(rows(f"cal_{counter}", "cal"))
+        copy_kib = [v for k, vs in cal.items() if "copyBuffer" in k for v in vs]
+        scale = copy_bytes / (max(copy_kib) * 1024.0)
+        ker = per_kernel(rows(f"pmc_{counter}", "pmc"))
+        name = max((k for k in ker if "k_fused" in k), key=lambda k: sum(ker[k]))
+        kib = sum(ker[name]) / len(ker[name])
+        out[counter] = {"kernel": name, "kib": kib, "scale": scale, "bytes": kib * 1024.0 * scale,
+                        "dispatches": len(ker[name])}
+    w_nodes = 1
+    import synth
+    w_nodes = synth.WORKLOADS[workload].nodes
+    alg = algorithmic_bytes_per_lup(synth.WORKLOADS[workload].storage) * w_nodes
+    total = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
+    entry = {
+        "bytes_per_launch": int(round(total)),
+        "read_bytes_per_launch": int(round(out["FETCH_SIZE"]["bytes"])),
+        "write_bytes_per_launch": int(round(out["WRITE_SIZE"]["bytes"])),
+        "fetch_size_kib": out["FETCH_SIZE"]["kib"],
+        "write_size_kib": out["WRITE_SIZE"]["kib"],
+        "read_scale": out["FETCH_SIZE"]["scale"],
+        "write_scale": out["WRITE_SIZE"]["scale"],
+        "algorithmic_bytes_per_launch": alg,
+        "ratio_to_algorithmic": total / alg,
+        "kernel_symbol": out["FETCH_SIZE"]["kernel"],
+        "dispatches": [out["FETCH_SIZE"]["dispatches"], out["WRITE_SIZE"]["dispatches"]],
+        "source_digest": source_digest(),
+    }
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data.setdefault(workload, {})[kernel_key] = entry
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    return entry
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +355,14 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass", "fused_staged"])
     ap.add_argument("--calibrate", action="store_true",
                     help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="no GPU: read rocprofv3 counter CSVs under DIR (pmc_/cal_ FETCH_SIZE, WRITE_SIZE) and "
+                         "record the fused kernel's HBM bytes per launch in profiles/traffic.json")
     args = ap.parse_args(argv)
+
+    if args.write_traffic:
+        print(json.dumps(write_traffic(args.write_traffic, args.workload)), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
