@@ -571,11 +571,13 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
   c.G = p.G;
   c.psi_ref = p.psi_ref;
 
-  // Fused-kernel tiling: 32 x kFusedTY columns, z split into chunks only as
-  // far as needed to give every compute unit a workgroup.  Each chunk end
-  // re-reads the plane beyond it and restarts the pipeline, so long columns
-  // are cheaper; measured on the 256^3 float64 lattice, whole columns (one
-  // workgroup per compute unit) beat four chunks per column by 10%.
+  // Fused-kernel tiling: 32 x kFusedTY columns.  When the columns fit in one
+  // round of resident workgroups, z is split only as far as needed to give
+  // every compute unit a workgroup: each chunk end re-reads the plane beyond
+  // it and restarts the pipeline, and on the 256^3 float64 lattice whole
+  // columns beat four chunks per column by 10%.  Lattices that take several
+  // rounds anyway use 64-plane chunks: on 512^3 (float32 and float16) they
+  // ran 22% faster than whole 512-plane columns.
   FusedTiling& t = ctx->tiling;
   t.tiles_x = (p.nx + kFusedTX - 1) / kFusedTX;
   t.tiles_y = (p.ny + kFusedTY - 1) / kFusedTY;
@@ -586,6 +588,7 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
       cus = 256;
     const long long target = cus;
     long long want = (target + cols - 1) / cols;  // chunks wanted
+    if (cols >= target) want = p.nz / 64;
     if (want < 1) want = 1;
     int chunk = static_cast<int>((p.nz + want - 1) / want);
     if (chunk < 4) chunk = 4;
@@ -598,6 +601,9 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
       return LB_EINVAL;
     }
     t.total = static_cast<int>(total);
+    // every fused kernel runs one workgroup per compute unit (register or
+    // LDS bound), so a round of resident workgroups is one per unit
+    t.per_round = ((cus + kXCDs - 1) / kXCDs) * kXCDs;
   }
   c.Gf = static_cast<float>(p.G);
   c.psi_reff = static_cast<float>(p.psi_ref);

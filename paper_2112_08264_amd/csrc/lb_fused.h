@@ -56,13 +56,22 @@ struct FusedTiling {
   int chunk;             // planes per z-chunk
   int chunks;            // number of z-chunks
   int total;             // tiles_x * tiles_y * chunks
+  int per_round;         // workgroups resident at once (compute units x workgroups per unit), a multiple of 8
 };
 
-// Workgroup id -> work item, XCD-contiguous (see above).
-__device__ __forceinline__ int fused_work_item(int b, int total) {
-  const int q = total / kXCDs, r = total % kXCDs;
-  const int j = b % kXCDs, s = b / kXCDs;
-  return j * q + (j < r ? j : r) + s;
+// Workgroup id -> work item.  Workgroups are dispatched in id order, round
+// after round of `per_round`, and id modulo 8 picks the XCD.  Within each
+// round the XCD-contiguous numbering above applies, so that the columns
+// resident at one time form one compact block of consecutive tiles (their
+// halo rows then come from columns being marched at the same time, and
+// x-neighbours share an XCD's L2).
+__device__ __forceinline__ int fused_work_item(int b, int total, int per_round) {
+  const int base = (b / per_round) * per_round;
+  const int n = min(per_round, total - base);
+  const int bb = b - base;
+  const int q = n / kXCDs, r = n % kXCDs;
+  const int j = bb % kXCDs, s = bb / kXCDs;
+  return base + j * q + (j < r ? j : r) + s;
 }
 
 // RECORD: also write the moment record of the pre-collision state (rho_A,
@@ -85,7 +94,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
   __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
   __shared__ uint8_t ring_solid[SOLID ? NS : 1][SOLID ? RY : 1][SOLID ? RX : 1];
 
-  const int w = fused_work_item(blockIdx.x, t.total);
+  const int w = fused_work_item(blockIdx.x, t.total, t.per_round);
   const int chunk = w / (t.tiles_x * t.tiles_y);
   const int tile = w - chunk * (t.tiles_x * t.tiles_y);
   const int ty0 = (tile / t.tiles_x) * TY, tx0 = (tile % t.tiles_x) * TX;
@@ -318,7 +327,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
   constexpr int ST_SIDE = KI * 2 * RY;           // [ki][left rows -1 .. TY, right rows -1 .. TY]
   __shared__ real stage[STAGED ? ST_ROWS + ST_SIDE : 1];
 
-  const int w = fused_work_item(blockIdx.x, t.total);
+  const int w = fused_work_item(blockIdx.x, t.total, t.per_round);
   const int chunk = w / (t.tiles_x * t.tiles_y);
   const int tile = w - chunk * (t.tiles_x * t.tiles_y);
   const int ty0 = (tile / t.tiles_x) * TY, tx0 = (tile % t.tiles_x) * TX;
