@@ -287,3 +287,81 @@ def test_full_size_spinodal256_sampled_one_step_parity():
         got = f1[:, :, z, y, x].cpu().numpy()
         err = np.max(np.abs(got - want[s]) / np.maximum(np.abs(want[s]), 1e-3 * O.W[None, :]))
         assert err <= 1e-13, (x, y, z, err)
+
+
+def _gather_block(torch, f5, solid3, site, r=2):
+    """Populations (2, 19, 2r+1, 2r+1, 2r+1) and solid flags around ``site``
+    (periodic), copied to the host.  One step at the block's centre depends
+    only on nodes within distance 2, so the per-node twin can step the block
+    as if it were a periodic box of its own."""
+    nz, ny, nx = f5.shape[2:]
+    x, y, z = (int(v) for v in site)
+    dev = f5.device
+    zi = torch.tensor([(z + d) % nz for d in range(-r, r + 1)], device=dev)
+    yi = torch.tensor([(y + d) % ny for d in range(-r, r + 1)], device=dev)
+    xi = torch.tensor([(x + d) % nx for d in range(-r, r + 1)], device=dev)
+    blk = f5.index_select(2, zi).index_select(3, yi).index_select(4, xi).cpu().numpy()
+    sol = None
+    if solid3 is not None:
+        sol = solid3.index_select(0, zi).index_select(1, yi).index_select(2, xi).cpu().numpy()
+    return blk, sol
+
+
+@pytest.mark.parametrize("wname", ["spinodal256_f32", "spinodal256_f16s", "spheres512_f32"])
+def test_full_size_reduced_storage_sampled_one_step(wname):
+    """The float32 and float16-shifted forms at their benchmark sizes (256^3,
+    and 512^3 with 2000 spheres), in the launch configuration the benchmark
+    times: after 20 GPU steps, one more GPU step at sampled nodes against the
+    float64 per-node twin stepped from the exported GPU state.  The bound is
+    the storage's rounding of the result -- half an ulp of float16 at
+    |f - w_i rho0| for the shifted form -- plus float32 arithmetic (1e-5 w_i)."""
+    torch = _torch()
+    w = synth.WORKLOADS[wname]
+    shape, n = w.shape, w.nodes
+    _say(f"case {wname} full-size sampled one-step parity")
+    a, b = synth.fluid_fields(shape, w.amp, w.seed)
+    solid = None
+    sites = [tuple(int(v) for v in s) for s in synth.sample_sites(shape, 12, 71)]
+    if w.spheres:
+        centres = synth.sphere_centres(shape, w.spheres, w.radius, w.sphere_seed)
+        solid = synth.solid_mask(shape, centres, w.radius)
+        sites = [s for s in sites if not solid[s[2], s[1], s[0]]]
+        # fluid nodes next to a sphere, to exercise bounce-back
+        nz, ny, nx = shape
+        for cx, cy, cz in centres[:60]:
+            x, y, z = (int(round(cx)) + 6) % nx, int(round(cy)) % ny, int(round(cz)) % nz
+            if solid[z, y, x]:
+                continue
+            near = any(solid[(z + dz) % nz, (y + dy) % ny, (x + dx) % nx]
+                       for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+            if near:
+                sites.append((x, y, z))
+            if len(sites) >= 24:
+                break
+        assert len(sites) >= 18
+    with P.Lattice(shape, tau=w.tau, G=w.G, storage=w.storage) as lat:
+        lat.set_fields(a.ravel().copy(), b.ravel().copy(), None,
+                       None if solid is None else solid.reshape(-1).astype(np.uint8).copy())
+        lat.step(20)
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        f5 = f.view(2, 19, *shape)
+        s3 = None if solid is None else torch.tensor(solid.astype(np.uint8), device="cuda")
+        blocks = [_gather_block(torch, f5, s3, s) for s in sites]
+        lat.step(1)
+        lat.get_populations(f)
+        got = [f5[:, :, z, y, x].cpu().numpy() for (x, y, z) in sites]
+        _, nonfinite = lat.totals()
+    assert not nonfinite
+    shift = (O.W[None, :] * np.asarray(w.rho0)[:, None]) if w.storage == "f16s" else 0.0
+    worst = 0.0
+    for (x, y, z), (blk, sol), g in zip(sites, blocks, got):
+        want = N.step_at(blk, [(2, 2, 2)], w.tau, w.G, solid=sol)[0]
+        bound = 1e-5 * O.W[None, :]
+        if w.storage == "f16s":
+            bound = bound + 2.0 ** -11 * 1.01 * np.abs(want - shift)
+        ratio = np.max(np.abs(g - want) / bound)
+        worst = max(worst, ratio)
+        assert ratio <= 1.0, (x, y, z, ratio)
+    _say(f"  worst error / bound {worst:.3f} over {len(sites)} sites")
+
