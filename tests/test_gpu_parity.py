@@ -112,6 +112,19 @@ def test_f64_staged_kernel_bitwise_equal_to_oracle(shape):
     assert np.array_equal(got, ref)
 
 
+def test_f64_tiling_with_several_rounds_of_workgroups_bitwise():
+    """A lattice with as many 32 x 8 columns as the GPU has compute units
+    (256): the columns are cut into 64-plane chunks and numbered round by
+    round; every node must still be stepped exactly once."""
+    shape = (128, 2048, 32)
+    _say(f"case f64 several rounds of workgroups shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.05, 25)
+    p = O.Params((0.9, 1.1), 3.5)
+    ref = O.step(O.init_equilibrium(a, b), p, n=2)
+    got = run_gpu(shape, p.tau, p.G, a, b, 2)
+    assert np.array_equal(got, ref)
+
+
 def test_f64_staged_kernel_solids_match_oracle():
     shape = (12, 14, 32)
     _say(f"case f64 staged solids shape={shape}")
