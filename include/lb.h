@@ -147,9 +147,10 @@ const char* lb_timing_name(int32_t slot);
  * once per step: one kernel marches z-columns and keeps the pseudopotential
  * of three planes in LDS.  LB_KERNEL_FUSED_STAGED (the default;
  * LB_KERNEL_AUTO picks it) is the same march for LB_F64 with nx a multiple
- * of 32, where the populations of the plane two ahead are copied into LDS by
- * direct-to-LDS loads while the current plane is collided; other storages
- * and shapes run LB_KERNEL_FUSED.  LB_KERNEL_TWO_PASS computes the
+ * of 32 and no solid nodes, where the populations of the plane two ahead are
+ * copied into LDS by direct-to-LDS loads while the current plane is
+ * collided; other storages, shapes and lattices with solids run
+ * LB_KERNEL_FUSED.  LB_KERNEL_TWO_PASS computes the
  * pseudopotential field in a first kernel and collides and streams in a
  * second.  All give bitwise identical results for LB_F64.
  * Errors: LB_EINVAL (unknown value). */

@@ -182,8 +182,8 @@ const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->ma
 // Typed implementations
 // ---------------------------------------------------------------------------
 // One fused step from fin to fout.  float64: component-pair waves, either
-// without prefetch or (LB_KERNEL_FUSED_STAGED, nx a multiple of 32) with the
-// plane two ahead staged into LDS by direct-to-LDS loads; float32
+// without prefetch or (LB_KERNEL_FUSED_STAGED, nx a multiple of 32, no
+// solids) with the plane two ahead staged into LDS by direct-to-LDS loads; float32
 // arithmetic: single-component waves with a register prefetch depth of three
 // planes.  With rec != nullptr the kernel also writes the moment record of
 // the pre-collision state for the adjoint.
@@ -196,10 +196,13 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
   const uint8_t* m = SOLID ? ctx->mask : nullptr;
   const dim3 grid(t.total), block(64 * kFusedTY);
   if constexpr (ST == ST_F64) {
-    if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_fits(ctx))
-      k_fused_pair<ST, SOLID, kFusedTY, RECORD, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
-    else
-      k_fused_pair<ST, SOLID, kFusedTY, RECORD, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+    if constexpr (!SOLID) {
+      if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_fits(ctx)) {
+        k_fused_pair<ST, false, kFusedTY, RECORD, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        return;
+      }
+    }
+    k_fused_pair<ST, SOLID, kFusedTY, RECORD, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   } else {
     k_fused<ST, SOLID, kFusedTY, 3, RECORD><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   }

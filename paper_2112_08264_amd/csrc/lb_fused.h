@@ -319,6 +319,9 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
   static_assert(2 * (2 * RX + 2 * TY) <= 64 * TY, "too few lanes for the halo tasks");
   static_assert(!STAGED || (sizeof(store_t<ST>) == 8 && TY % 2 == 0 && 4 * (TY + 2) <= 64),
                 "the stage layout assumes float64, and one wave covers the side columns");
+  // With solids the staged variant needs more than the 256 registers two
+  // waves per SIMD allow and spills; the unstaged kernel is faster there.
+  static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
   constexpr int NQ = ((TY + 2) * 16 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -458,16 +461,8 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
     // STAGED: plane z + 2 is loaded while plane z is collided; its psi is
     // needed unless z + 1 is the chunk's far neighbour plane.
     const bool more = j + 2 <= zlen;
-    bool n_solid = false, nh_solid = false;
     if constexpr (STAGED) {
-      if (more) {
-        const int zz = (z + 2) % g.nz;
-        stage_issue(zz);
-        if constexpr (SOLID) {
-          n_solid = mask[row + plane_n * zz] != 0;
-          if (has_halo) nh_solid = mask[hrow + plane_n * zz] != 0;
-        }
-      }
+      if (more) stage_issue((z + 2) % g.nz);
     } else {
       fill(sp, wrapz(z + 1), nxt);
       __syncthreads();
@@ -577,8 +572,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
 #pragma unroll
             for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * 2 * RY];
           }
-          ring[sm][hk][hy + 1][hx + 1] = (SOLID && nh_solid) ? real(0) : pseudopotential(density<real>(h), coef_ref<real>(c));
-          if constexpr (SOLID) if (hk == 0) ring_solid[sm][hy + 1][hx + 1] = nh_solid;
+          ring[sm][hk][hy + 1][hx + 1] = pseudopotential(density<real>(h), coef_ref<real>(c));
         }
         if (store) push(cur, bounced);
 #pragma unroll
@@ -586,8 +580,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
           cur[i] = nxt[i];
           nxt[i] = stage[ibase + i * RY * TX];
         }
-        ring[sm][k][ly + 1][lx + 1] = (SOLID && n_solid) ? real(0) : pseudopotential(density<real>(nxt), coef_ref<real>(c));
-        if constexpr (SOLID) if (k == 0) ring_solid[sm][ly + 1][lx + 1] = n_solid;
+        ring[sm][k][ly + 1][lx + 1] = pseudopotential(density<real>(nxt), coef_ref<real>(c));
       } else {
         if (store) push(cur, bounced);
 #pragma unroll

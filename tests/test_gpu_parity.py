@@ -125,7 +125,8 @@ def test_f64_tiling_with_several_rounds_of_workgroups_bitwise():
     assert np.array_equal(got, ref)
 
 
-def test_f64_staged_kernel_solids_match_oracle():
+def test_f64_staged_selection_with_solids_matches_oracle():
+    """With solid nodes the staged selection runs the unstaged kernel."""
     shape = (12, 14, 32)
     _say(f"case f64 staged solids shape={shape}")
     centres = synth.sphere_centres(shape, 4, 2.5, 33)
