@@ -77,19 +77,28 @@ __device__ __forceinline__ int fused_work_item(int b, int total, int per_round) 
 // RECORD: also write the moment record of the pre-collision state (rho_A,
 // rho_B, m_A, m_B, psi_A, psi_B as [10][N], zero at solid nodes) that the
 // adjoint step consumes.
-template <int ST, bool SOLID, int TY, int D, bool RECORD>
-__global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
-                                                   const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c,
-                                                   FusedTiling t, real_t<ST>* __restrict__ rec) {
+//
+// TX = 32: each wave carries two rows of 32 nodes; TX = 64: one row of 64
+// (whole 128-byte lines of float16 rows, fewer partly written lines at the
+// tile's x edges).  A workgroup has 2 TY / (64 / TX) waves.
+template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX>
+__global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>* __restrict__ fin,
+                                                              store_t<ST>* __restrict__ fout,
+                                                              const uint8_t* __restrict__ mask, Geometry g,
+                                                              StepCoeffs c, FusedTiling t,
+                                                              real_t<ST>* __restrict__ rec) {
   using real = real_t<ST>;
   using store = store_t<ST>;
-  constexpr int TX = kFusedTX;
+  constexpr int RPW = 64 / TX;             // rows per wave
   constexpr int RX = TX + 2, RY = TY + 2;  // ring plane incl. halo
   constexpr int NS = D + 2;                // ring slots: planes z - 1 .. z + D
   constexpr int NX = D + 1;                // exchange slots: planes z .. z + D
+  constexpr bool CORNERS_IN_ROWS = RX <= 64;  // else the four corners go with the side columns
   static_assert(D >= 2, "psi of plane z + 1 must be ready before plane z is collided");
   static_assert(sizeof(real) == 4, "float arithmetic only; float64 storage runs k_fused_pair");
-  static_assert(TY % 2 == 0 && TY >= 6, "three row-pairs per component carry the halo");
+  static_assert(TX == 32 || TX == 64, "a wave covers two rows of 32 or one row of 64");
+  static_assert(TY % RPW == 0 && TY / RPW >= 3, "three waves per component carry the halo");
+  static_assert(2 * TY + (CORNERS_IN_ROWS ? 0 : 4) <= 64, "one wave carries the side columns");
   __shared__ real ring[NS][2][RY][RX];
   __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
   __shared__ uint8_t ring_solid[SOLID ? NS : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -103,8 +112,8 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k = __builtin_amdgcn_readfirstlane(wave & 1);    // component of this wave
-  const int rp = __builtin_amdgcn_readfirstlane(wave >> 1);  // row pair
-  const int lx = lane & 31, ly = 2 * rp + (lane >> 5);
+  const int rp = __builtin_amdgcn_readfirstlane(wave >> 1);  // row group of this wave
+  const int lx = lane % TX, ly = RPW * rp + lane / TX;
   // interior node of this lane, wrapped into the box (lanes past the box edge
   // read the wrapped node so that every ring slot holds the right psi)
   const int gx = (tx0 + lx) % g.nx, gy = (ty0 + ly) % g.ny;
@@ -112,13 +121,21 @@ __global__ void __launch_bounds__(64 * TY) k_fused(const store_t<ST>* __restrict
   const uint32_t row = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy;
   const uint32_t plane_n = (uint32_t)g.nx * (uint32_t)g.ny;
 
-  // halo node of this lane: row pair 0 -> row above, 1 -> row below,
-  // 2 -> left and right columns, others none
+  // halo node of this lane: row group 0 -> row above, 1 -> row below,
+  // 2 -> left and right columns (and the corners when a row has more than
+  // 64 ring nodes), others none
   bool has_halo = false;
   int hx = 0, hy = 0;
-  if (rp == 0 && lane < RX) { has_halo = true; hx = lane - 1; hy = -1; }
-  if (rp == 1 && lane < RX) { has_halo = true; hx = lane - 1; hy = TY; }
+  constexpr int x_lo = CORNERS_IN_ROWS ? -1 : 0, nrow = CORNERS_IN_ROWS ? RX : TX;
+  if (rp == 0 && lane < nrow) { has_halo = true; hx = lane + x_lo; hy = -1; }
+  if (rp == 1 && lane < nrow) { has_halo = true; hx = lane + x_lo; hy = TY; }
   if (rp == 2 && lane < 2 * TY) { has_halo = true; hx = lane < TY ? -1 : TX; hy = lane < TY ? lane : lane - TY; }
+  if (!CORNERS_IN_ROWS && rp == 2 && lane >= 2 * TY && lane < 2 * TY + 4) {
+    const int cn = lane - 2 * TY;
+    has_halo = true;
+    hx = (cn & 1) ? TX : -1;
+    hy = (cn & 2) ? TY : -1;
+  }
   const int hgx = ((tx0 + hx) % g.nx + g.nx) % g.nx;
   const int hgy = ((ty0 + hy) % g.ny + g.ny) % g.ny;
   const uint32_t hrow = (uint32_t)hgx + (uint32_t)g.nx * (uint32_t)hgy;
