@@ -219,9 +219,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_r(const real_t<ST>* __restrict__
 #pragma unroll
     for (int l = 1; l < Q; ++l) {
       const long long src = nb[OPP[l]];  // x - c_l
-      T += weight<real>(l) * (real(CX[l]) * Win[(long long)(3 * kb + 0) * g.N + src] +
-                              real(CY[l]) * Win[(long long)(3 * kb + 1) * g.N + src] +
-                              real(CZ[l]) * Win[(long long)(3 * kb + 2) * g.N + src]);
+      // c_l . W with the zero components left out (adding a zero product
+      // changes no finite sum), which halves the gathered loads
+      real cw = real(0);
+      if (CX[l] != 0) cw = cw + real(CX[l]) * Win[(long long)(3 * kb + 0) * g.N + src];
+      if (CY[l] != 0) cw = cw + real(CY[l]) * Win[(long long)(3 * kb + 1) * g.N + src];
+      if (CZ[l] != 0) cw = cw + real(CZ[l]) * Win[(long long)(3 * kb + 2) * g.N + src];
+      T += weight<real>(l) * cw;
     }
     const real rho = mom[(long long)k * g.N + n];
     r[(long long)k * g.N + n] = -exp_real<real>(-rho / ref) * T;
