@@ -35,6 +35,12 @@ constexpr int kFusedTY = 8;   // float64 fused tiles: 32 x 8 nodes, one row per 
 // fewer lines are written in part at the tile's x edges.
 constexpr int kFloatTX = 64;
 constexpr int kFloatTY = 4;
+// Staged float64 step on 64 x 4 tiles (two waves per row) where nx allows:
+// 9% faster than 32 x 8 at 256^3 -- half as many tile edges in x, where a
+// push store writes a 128-byte line only in part.  The unstaged kernel was
+// slower on 64 x 4 tiles and keeps 32 x 8.
+constexpr int kWideTX = 64;
+constexpr int kWideTY = 4;
 
 constexpr int kTotalsMaxBlocks = 2048;
 
@@ -78,7 +84,8 @@ struct lb_ctx {
   double* adj_dG = nullptr;           // running dJ/dG
   bool adj_ready = false;
   int kernel = LB_KERNEL_FUSED_STAGED;  // LB_KERNEL_AUTO
-  FusedTiling tiling{};
+  FusedTiling tiling{};       // the storage's default fused kernel
+  FusedTiling tiling_wide{};  // staged float64 kernel on 64 x 4 tiles (nx a multiple of 64)
   int64_t bytes = 0;
 };
 
@@ -189,28 +196,39 @@ const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->ma
 // ---------------------------------------------------------------------------
 // One fused step from fin to fout.  float64: component-pair waves, either
 // without prefetch or (LB_KERNEL_FUSED_STAGED, nx a multiple of 32, no
-// solids) with the plane two ahead staged into LDS by direct-to-LDS loads; float32
-// arithmetic: single-component waves with a register prefetch depth of three
-// planes.  With rec != nullptr the kernel also writes the moment record of
+// solids) with the plane two ahead staged into LDS by direct-to-LDS loads,
+// on 64 x 4 tiles when nx is a multiple of 64; float32 arithmetic:
+// single-component waves with a register prefetch depth of three planes.  With rec != nullptr the kernel also writes the moment record of
 // the pre-collision state for the adjoint.
 bool staged_fits(const lb_ctx* ctx) { return ctx->p.storage == LB_F64 && ctx->p.nx % kFusedTX == 0; }
+bool staged_wide(const lb_ctx* ctx) { return ctx->p.storage == LB_F64 && ctx->p.nx % kWideTX == 0; }
 
 template <int ST, bool SOLID, bool RECORD>
 void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
                      typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
-  const FusedTiling t = ctx->tiling;
   const uint8_t* m = SOLID ? ctx->mask : nullptr;
-  const dim3 grid(t.total), block(ST == ST_F64 ? 64 * kFusedTY : 128 * kFloatTY * kFloatTX / 64);
   if constexpr (ST == ST_F64) {
     if constexpr (!SOLID) {
+      if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx)) {
+        const FusedTiling t = ctx->tiling_wide;
+        k_fused_pair<ST, false, kWideTY, RECORD, true, kWideTX>
+            <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        return;
+      }
       if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_fits(ctx)) {
-        k_fused_pair<ST, false, kFusedTY, RECORD, true><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+        const FusedTiling t = ctx->tiling;
+        k_fused_pair<ST, false, kFusedTY, RECORD, true>
+            <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
         return;
       }
     }
-    k_fused_pair<ST, SOLID, kFusedTY, RECORD, false><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+    const FusedTiling t = ctx->tiling;
+    k_fused_pair<ST, SOLID, kFusedTY, RECORD, false>
+        <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   } else {
-    k_fused<ST, SOLID, kFloatTY, 3, RECORD, kFloatTX><<<grid, block, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
+    const FusedTiling t = ctx->tiling;
+    k_fused<ST, SOLID, kFloatTY, 3, RECORD, kFloatTX>
+        <<<dim3(t.total), dim3(128 * kFloatTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   }
 }
 
@@ -527,6 +545,37 @@ const char* lb_timing_name(int32_t slot) {
   return kSlotNames[slot];
 }
 
+// Fused-kernel tiling: columns of tile_x x tile_y nodes.  When the columns
+// fit in one round of resident workgroups, z is split only as far as needed
+// to give every compute unit a workgroup: each chunk end re-reads the plane
+// beyond it and restarts the pipeline, and on the 256^3 float64 lattice
+// whole columns beat four chunks per column by 10%.  Lattices that take
+// several rounds anyway use 64-plane chunks: on 512^3 (float32 and float16)
+// they ran 22% faster than whole 512-plane columns.
+bool make_tiling(const lb_params& p, int tile_x, int tile_y, int cus, FusedTiling* out) {
+  FusedTiling t{};
+  t.tiles_x = (p.nx + tile_x - 1) / tile_x;
+  t.tiles_y = (p.ny + tile_y - 1) / tile_y;
+  const long long cols = static_cast<long long>(t.tiles_x) * t.tiles_y;
+  const long long target = cus;
+  long long want = (target + cols - 1) / cols;  // chunks wanted
+  if (cols >= target) want = p.nz / 64;
+  if (want < 1) want = 1;
+  int chunk = static_cast<int>((p.nz + want - 1) / want);
+  if (chunk < 4) chunk = 4;
+  if (chunk > p.nz) chunk = p.nz;
+  t.chunk = chunk;
+  t.chunks = (p.nz + chunk - 1) / chunk;
+  const long long total = cols * t.chunks;
+  if (total > 0x7fffffffLL) return false;
+  t.total = static_cast<int>(total);
+  // every fused kernel runs one workgroup per compute unit (register or
+  // LDS bound), so a round of resident workgroups is one per unit
+  t.per_round = ((cus + kXCDs - 1) / kXCDs) * kXCDs;
+  *out = t;
+  return true;
+}
+
 lb_status lb_create(const lb_params* params, lb_ctx** out) {
   if (out == nullptr) return LB_EINVAL;
   *out = nullptr;
@@ -580,41 +629,17 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
   c.G = p.G;
   c.psi_ref = p.psi_ref;
 
-  // Fused-kernel tiling: columns of 32 x 8 (float64) or 64 x 4 nodes.  When
-  // the columns fit in one round of resident workgroups, z is split only as
-  // far as needed to give every compute unit a workgroup: each chunk end re-reads the plane beyond
-  // it and restarts the pipeline, and on the 256^3 float64 lattice whole
-  // columns beat four chunks per column by 10%.  Lattices that take several
-  // rounds anyway use 64-plane chunks: on 512^3 (float32 and float16) they
-  // ran 22% faster than whole 512-plane columns.
-  FusedTiling& t = ctx->tiling;
-  const int tile_x = p.storage == LB_F64 ? kFusedTX : kFloatTX;
-  const int tile_y = p.storage == LB_F64 ? kFusedTY : kFloatTY;
-  t.tiles_x = (p.nx + tile_x - 1) / tile_x;
-  t.tiles_y = (p.ny + tile_y - 1) / tile_y;
   {
-    const long long cols = static_cast<long long>(t.tiles_x) * t.tiles_y;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p.device) != hipSuccess || cus < 1)
       cus = 256;
-    const long long target = cus;
-    long long want = (target + cols - 1) / cols;  // chunks wanted
-    if (cols >= target) want = p.nz / 64;
-    if (want < 1) want = 1;
-    int chunk = static_cast<int>((p.nz + want - 1) / want);
-    if (chunk < 4) chunk = 4;
-    if (chunk > p.nz) chunk = p.nz;
-    t.chunk = chunk;
-    t.chunks = (p.nz + chunk - 1) / chunk;
-    const long long total = cols * t.chunks;
-    if (total > 0x7fffffffLL) {
+    const bool f64 = p.storage == LB_F64;
+    bool ok = make_tiling(p, f64 ? kFusedTX : kFloatTX, f64 ? kFusedTY : kFloatTY, cus, &ctx->tiling);
+    if (ok && f64 && p.nx % kWideTX == 0) ok = make_tiling(p, kWideTX, kWideTY, cus, &ctx->tiling_wide);
+    if (!ok) {
       delete ctx;
       return LB_EINVAL;
     }
-    t.total = static_cast<int>(total);
-    // every fused kernel runs one workgroup per compute unit (register or
-    // LDS bound), so a round of resident workgroups is one per unit
-    t.per_round = ((cus + kXCDs - 1) / kXCDs) * kXCDs;
   }
   c.Gf = static_cast<float>(p.G);
   c.psi_reff = static_cast<float>(p.psi_ref);

@@ -325,21 +325,26 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 // 32 nodes + 20 side nodes) float64 = 103,360 bytes, so one workgroup per
 // compute unit.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED>
-__global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
-                                                        store_t<ST>* __restrict__ fout,
-                                                        const uint8_t* __restrict__ mask, Geometry g,
-                                                        StepCoeffs c, FusedTiling t, real_t<ST>* __restrict__ rec) {
+//
+// TX = 32 or 64 nodes per tile row; a row is carried by TX / 32 waves.
+template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX>
+__global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
+                                                            store_t<ST>* __restrict__ fout,
+                                                            const uint8_t* __restrict__ mask, Geometry g,
+                                                            StepCoeffs c, FusedTiling t,
+                                                            real_t<ST>* __restrict__ rec) {
   using real = real_t<ST>;
-  constexpr int TX = kFusedTX;
+  constexpr int WPR = TX / 32;  // waves per tile row
+  constexpr int NW = TY * WPR;  // waves per workgroup
   constexpr int RX = TX + 2, RY = TY + 2;
-  static_assert(2 * (2 * RX + 2 * TY) <= 64 * TY, "too few lanes for the halo tasks");
+  static_assert(TX == 32 || TX == 64, "a wave carries 32 nodes of a row");
+  static_assert(2 * (2 * RX + 2 * TY) <= 64 * NW, "too few lanes for the halo tasks");
   static_assert(!STAGED || (sizeof(store_t<ST>) == 8 && TY % 2 == 0 && 4 * (TY + 2) <= 64),
                 "the stage layout assumes float64, and one wave covers the side columns");
   // With solids the staged variant needs more than the 256 registers two
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
-  constexpr int NQ = ((TY + 2) * 16 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
+  constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
   constexpr int KI = 2 * Q;                      // population planes of both components
@@ -356,7 +361,7 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k = lane >> 5;
-  const int lx = lane & 31, ly = wave;
+  const int lx = (wave % WPR) * 32 + (lane & 31), ly = wave / WPR;
   const int gx = (tx0 + lx) % g.nx, gy = (ty0 + ly) % g.ny;
   const bool active = (tx0 + lx) < g.nx && (ty0 + ly) < g.ny;
   const long long row = (long long)gx + (long long)g.nx * gy;
@@ -385,10 +390,10 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
 
   // ---- direct-to-LDS staging (STAGED only) ----
   // Byte offsets within one z-plane of a population plane.  Rows: chunk
-  // c = 64 q + lane (c < 160) covers row c / 16 - 1 of the tile and x =
-  // 2 (c % 16), 2 (c % 16) + 1 (16 bytes).  Sides: lane < 40 covers one half
-  // of the float64 at side node lane / 2 (left column for < 10, right
-  // column after, rows -1 .. TY).
+  // c = 64 q + lane (c < RY TX / 2) covers row c / (TX / 2) - 1 of the tile
+  // and x = 2 (c % (TX / 2)) and the next node (16 bytes).  Sides: lane <
+  // 4 RY covers one half of the float64 at side node lane / 2 (left column
+  // for < RY, right column after, rows -1 .. TY).
   uint32_t voff16[NQ] = {}, voff4 = 0;
   bool on16[NQ] = {}, on4 = false;
   int ibase = 0, hbase = 0;  // stage index of value 0 of this lane's interior node and halo node
@@ -398,8 +403,8 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int cq = 64 * q + lane;
-      on16[q] = cq < RY * 16;
-      const int r = cq >> 4, xp = cq & 15;
+      on16[q] = cq < RY * (TX / 2);
+      const int r = cq / (TX / 2), xp = cq % (TX / 2);
       voff16[q] = (uint32_t)(((uint32_t)(tx0 + 2 * xp) + (uint32_t)g.nx * (uint32_t)wrapy(ty0 + r - 1)) * 8u);
     }
     on4 = lane < 4 * RY;
@@ -413,22 +418,22 @@ __global__ void __launch_bounds__(64 * TY) k_fused_pair(const store_t<ST>* __res
     hbase = hrows ? (hk * Q * RY + hy + 1) * TX + hx : ST_ROWS + hk * Q * 2 * RY + (hx < 0 ? 0 : RY) + hy + 1;
   }
   // Issue the loads of plane zz into the stage.  Wave w copies population
-  // planes ki = w, w + 8, ... (uniform per wave).
+  // planes ki = w, w + NW, ... (uniform per wave).
   auto stage_issue = [&](int zz) {
     typedef __attribute__((address_space(3))) void lds_void;
     typedef __attribute__((address_space(1))) void glb_void;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const char* zbase = reinterpret_cast<const char*>(fin) + (size_t)plane_n * (size_t)zz * 8u;
 #pragma unroll
-    for (int m = 0; m < (KI + TY - 1) / TY; ++m) {
-      const int ki = wv + TY * m;
+    for (int m = 0; m < (KI + NW - 1) / NW; ++m) {
+      const int ki = wv + NW * m;
       if (ki < KI) {
         const char* base = zbase + (size_t)ki * (size_t)g.Npad * 8u;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
           if (on16[q])
             __builtin_amdgcn_global_load_lds((glb_void*)(base + voff16[q]),
-                                             (lds_void*)(&stage[(ki * RY + 4 * q) * TX]), 16, 0, 0);
+                                             (lds_void*)(&stage[ki * RY * TX + 128 * q]), 16, 0, 0);
         if (on4) __builtin_amdgcn_global_load_lds((glb_void*)(base + voff4), (lds_void*)(&stage[ST_ROWS + ki * 2 * RY]), 4, 0, 0);
       }
     }

@@ -97,10 +97,12 @@ def test_f64_solids_match_oracle(kernel):
     assert np.all(got[:, :, solid.astype(bool)] == 0.0)
 
 
-# The staged kernel runs when nx is a multiple of 32 (other shapes fall back
-# to the plain fused kernel): rows past a short y extent, a single plane,
-# several tiles along x, chunks of one plane.
-@pytest.mark.parametrize("shape", [(4, 4, 32), (3, 5, 32), (1, 1, 32), (2, 9, 96), (5, 8, 64), (69, 3, 32)])
+# The staged kernel runs when nx is a multiple of 32, on 64 x 4 tiles when nx
+# is a multiple of 64 (other shapes fall back to the plain fused kernel):
+# rows past a short y extent, a single plane, several tiles along x, chunks
+# of one plane, for both tile shapes.
+@pytest.mark.parametrize("shape", [(4, 4, 32), (3, 5, 32), (1, 1, 32), (2, 9, 96), (69, 3, 32),
+                                   (5, 8, 64), (3, 3, 64), (1, 1, 64), (2, 9, 192), (69, 5, 64)])
 def test_f64_staged_kernel_bitwise_equal_to_oracle(shape):
     _say(f"case f64 staged bitwise shape={shape}")
     a, b = synth.fluid_fields(shape, 0.2, 23)
@@ -112,11 +114,11 @@ def test_f64_staged_kernel_bitwise_equal_to_oracle(shape):
     assert np.array_equal(got, ref)
 
 
-def test_f64_tiling_with_several_rounds_of_workgroups_bitwise():
-    """A lattice with as many 32 x 8 columns as the GPU has compute units
-    (256): the columns are cut into 64-plane chunks and numbered round by
-    round; every node must still be stepped exactly once."""
-    shape = (128, 2048, 32)
+@pytest.mark.parametrize("shape", [(128, 2048, 32), (128, 1024, 64)])
+def test_f64_tiling_with_several_rounds_of_workgroups_bitwise(shape):
+    """A lattice with as many 32 x 8 (or 64 x 4) columns as the GPU has
+    compute units (256): the columns are cut into 64-plane chunks and
+    numbered round by round; every node must still be stepped exactly once."""
     _say(f"case f64 several rounds of workgroups shape={shape}")
     a, b = synth.fluid_fields(shape, 0.05, 25)
     p = O.Params((0.9, 1.1), 3.5)
