@@ -8,7 +8,9 @@
 // are read from HBM once and stay in registers until their plane is
 // collided; the halo's populations belong to neighbouring columns that are
 // marched at the same time, so re-reading them mostly hits the caches.  Each
-// chunk also reads the plane before and the plane after it.
+// chunk also reads the plane before and the plane after it.  (This
+// describes k_fused, the float32 / float16 kernel; the float64 kernel
+// k_fused_pair further down is described there.)
 //
 // Software pipeline of depth D >= 2 (one barrier per plane): iteration z
 // issues the loads of plane z + D, collides plane z (psi of z - 1, z, z + 1
@@ -18,9 +20,9 @@
 // stores, waiting for them never waits for the stores.  Interior populations
 // of planes z .. z + D - 1 stay in registers.
 //
-// Lane layout: TX = 32.  Each wave carries one component for two rows of the
-// tile (lanes 0..31 row 2r, lanes 32..63 row 2r + 1), so every population
-// plane it touches has a wave-uniform base address.  The other component's
+// Lane layout: each wave carries one component for one row of TX = 64 nodes
+// or two rows of TX = 32, so every population plane it touches has a
+// wave-uniform base address.  The other component's
 // density and momentum at the same node, needed for the common velocity,
 // come from an LDS exchange written one iteration ahead.
 //
@@ -29,8 +31,9 @@
 // populations in the library's structure-of-arrays layout.
 //
 // Workgroups are numbered so that the ones the hardware sends to the same
-// XCD (workgroup id modulo 8) take a contiguous run of tiles of one z-chunk:
-// neighbouring columns then share that XCD's L2 for their halo reads.
+// XCD (workgroup id modulo 8) take a contiguous run of tiles of one z-chunk
+// (see fused_work_item): neighbouring columns then share that XCD's L2 for
+// their halo reads.
 #pragma once
 
 #include "lb_kernels.h"
@@ -302,18 +305,19 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 }
 
 // ---------------------------------------------------------------------------
-// Component-pair variant (used for float64).  Each wave holds one row of
-// TX = 32 nodes for both components: lanes 0..31 carry component A, lanes
+// Component-pair variant (used for float64).  Each wave holds 32 nodes of
+// one tile row for both components: lanes 0..31 carry component A, lanes
 // 32..63 component B of the same nodes, and the partner lane (lane ^ 32)
 // supplies the other component's density and momentum by a lane shuffle.
-// Ring of three psi planes.
+// A tile row of TX = 32 or 64 nodes takes TX / 32 waves.  Ring of three psi
+// planes.
 //
 // STAGED = false: no prefetch.  The plane z + 1 loads go to registers and
 // are consumed in the same iteration, which keeps the float64 register
 // budget (two planes of 19 populations) within 256 VGPRs without spilling,
 // but leaves their latency exposed.
 //
-// STAGED = true (float64 storage, nx a multiple of 32, TY = 8): the
+// STAGED = true (float64 storage, nx a multiple of TX, no solids): the
 // populations of plane z + 2 -- the tile's rows -1 .. TY and its two side
 // columns, both components -- are copied from HBM straight into an LDS
 // stage by direct-to-LDS loads (global_load_lds, which bypass the
@@ -321,12 +325,10 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 // stores.  Their latency hides behind a whole collision without costing a
 // register.  After the wait, psi of plane z + 2 is formed from the stage and
 // the plane's interior populations move into registers for its own
-// collision two iterations later.  Stage: 38 population planes x (10 rows x
-// 32 nodes + 20 side nodes) float64 = 103,360 bytes, so one workgroup per
-// compute unit.
+// collision two iterations later.  Stage: 38 population planes x ((TY + 2)
+// rows x TX nodes + 2 (TY + 2) side nodes) float64: 120,384 bytes for
+// 64 x 4 tiles, 103,360 for 32 x 8, so one workgroup per compute unit.
 // ---------------------------------------------------------------------------
-//
-// TX = 32 or 64 nodes per tile row; a row is carried by TX / 32 waves.
 template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX>
 __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                             store_t<ST>* __restrict__ fout,
