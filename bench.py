@@ -38,10 +38,17 @@ def algorithmic_bytes_per_lup(storage: str) -> int:
 
 
 def source_digest() -> str:
+    """Hash of the kernel sources' code, comments and blank space left out,
+    so that counters taken on a kernel stay attached to it while only its
+    comments change."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
