@@ -47,6 +47,12 @@ ADJOINT = [
     ("stencil transpose uses own component", "O._shift(Wk[kb], C[j])", "O._shift(Wk[k], C[j])"),
 ]
 
+SINGLE = [
+    ("single: velocity not divided by rho", "u = [m[a] / den for a in range(3)]", "u = [m[a] for a in range(3)]"),
+    ("single: tau in place of omega", "om = 1.0 / tau", "om = tau"),
+    ("single: relaxation weights swapped", "fs = (1.0 - om) * f + om * feq", "fs = (1.0 - om) * feq + om * f"),
+]
+
 RUNNER = r"""
 import importlib.util, sys
 sys.path.insert(0, {root!r})
@@ -85,6 +91,13 @@ def test_forward_pins_catch_planted_mistake(name, old, new):
 def test_adjoint_pins_catch_planted_mistake(name, old, new):
     tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
     rc = _run_mutant("lb_adjoint.py", "oracle.lb_adjoint", "lb_adjoint", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
+@pytest.mark.parametrize("name,old,new", SINGLE, ids=[m[0] for m in SINGLE])
+def test_single_fluid_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_single.py")]
+    rc = _run_mutant("lb_single.py", "oracle.lb_single", "lb_single", old, new, tests)
     assert rc != 0, f"no pin failed for planted mistake: {name}"
 
 
