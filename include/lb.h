@@ -224,6 +224,28 @@ lb_status lb_adjoint_step_record(lb_ctx* ctx, const void* record);
 /* Bytes of device memory the context holds. */
 lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes);
 
+/* ---- Single-fluid step (the paper's case 1, Sec. 5) ----------------------
+ * One population set: rho = sum_i f_i, u = m / rho, BGK relaxation towards
+ * f^eq(rho, u) (Sec. 2, Eq. 1; Appendix, Eq. LEQ), push streaming with
+ * halfway bounce-back at solid nodes at rest (Appendix, Eq. LADDFLBE with
+ * the wall velocity set to zero), periodic box.  No inter-component force.
+ * Parameters come from lb_params: nx, ny, nz, tau[0] (> 1/2), rho0[0] (the
+ * float16 offset w_i rho0), storage, device and stream; the other fields
+ * are ignored.  Storage per step: 19 values read and 19 written per node.
+ * Ownership, streams and on_device flags work as for the two-component
+ * calls above; populations are [19][N] float64, u is [3][N], rho is [N].
+ * lb1_totals writes (M, P_x, P_y, P_z).  Errors as for the corresponding
+ * two-component calls. */
+typedef struct lb1_ctx lb1_ctx; /* opaque; owned by the library */
+lb_status lb1_create(const lb_params* params, lb1_ctx** out);
+lb_status lb1_destroy(lb1_ctx* ctx);
+lb_status lb1_set_stream(lb1_ctx* ctx, void* stream);
+lb_status lb1_set_fields(lb1_ctx* ctx, const double* rho, const double* u, const uint8_t* solid, int on_device);
+lb_status lb1_step(lb1_ctx* ctx, int32_t n);
+lb_status lb1_moments(lb1_ctx* ctx, double* rho, double* u, int on_device);
+lb_status lb1_get_populations(lb1_ctx* ctx, double* f, int on_device);
+lb_status lb1_totals(lb1_ctx* ctx, double out[4], int* nonfinite);
+
 /* Human-readable text for a status code. */
 const char* lb_strerror(lb_status status);
 

@@ -13,6 +13,7 @@
 #include "lb_adjoint.h"
 #include "lb_fused.h"
 #include "lb_kernels.h"
+#include "lb_single.h"
 
 using namespace lbd;
 
@@ -509,6 +510,57 @@ lb_status ensure_plane(lb_ctx* ctx) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Single-fluid step (lb1_*): one population set, no force.
+// ---------------------------------------------------------------------------
+struct lb1_ctx {
+  lb_params p{};
+  Geometry g{};
+  StepCoeffs c{};
+  size_t elem = 0;
+  size_t grid_bytes = 0;
+  void* grid[2] = {nullptr, nullptr};
+  int cur = 0;
+  uint8_t* mask = nullptr;
+  bool has_solid = false;
+  double* partial = nullptr;
+  double* result = nullptr;
+  int* flag = nullptr;
+  double* plane = nullptr;
+  bool has_state = false;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+template <typename F>
+lb_status by_storage_id(int storage, F&& f) {
+  switch (storage) {
+    case LB_F64: return f(std::integral_constant<int, ST_F64>{});
+    case LB_F32: return f(std::integral_constant<int, ST_F32>{});
+    case LB_F16_SHIFTED: return f(std::integral_constant<int, ST_F16S>{});
+    default: return LB_EINVAL;
+  }
+}
+
+lb_status alloc1(void** ptr, size_t bytes) {
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return LB_ENOMEM;
+  }
+  return LB_OK;
+}
+
+void free1(lb1_ctx* ctx) {
+  (void)hipStreamSynchronize(ctx->stream);
+  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->mask, ctx->partial, ctx->result, ctx->flag, ctx->plane};
+  for (void* b : bufs)
+    if (b != nullptr) (void)hipFree(b);
+}
+
+}  // namespace
+
 extern "C" {
 
 void lb_params_default(lb_params* p) {
@@ -1086,6 +1138,252 @@ lb_status lb_timing_read(lb_ctx* ctx, int32_t slot, double* total_ms, int64_t* l
   if (total_ms != nullptr) *total_ms = ctx->t_ms[slot];
   if (launches != nullptr) *launches = ctx->t_n[slot];
   return LB_OK;
+}
+
+// ---- single-fluid step -----------------------------------------------------
+lb_status lb1_create(const lb_params* params, lb1_ctx** out) {
+  if (out == nullptr) return LB_EINVAL;
+  *out = nullptr;
+  if (params == nullptr) return LB_EINVAL;
+  const lb_params& p = *params;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return LB_EINVAL;
+  if (!is_finite(p.tau[0]) || !(p.tau[0] > 0.5) || !is_finite(p.rho0[0])) return LB_EINVAL;
+  if (p.storage != LB_F64 && p.storage != LB_F32 && p.storage != LB_F16_SHIFTED) return LB_EINVAL;
+  const long long N = static_cast<long long>(p.nx) * p.ny * p.nz;
+  if (N > 0x7fffffffLL - 4096) return LB_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) {
+    (void)hipGetLastError();
+    return LB_EDEVICE;
+  }
+  if (p.device < 0 || p.device >= ndev) return LB_EDEVICE;
+  DeviceGuard dg(p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  lb1_ctx* ctx = new (std::nothrow) lb1_ctx();
+  if (ctx == nullptr) return LB_ENOMEM;
+  ctx->p = p;
+  ctx->stream = static_cast<hipStream_t>(p.stream);
+  ctx->g.nx = p.nx;
+  ctx->g.ny = p.ny;
+  ctx->g.nz = p.nz;
+  ctx->g.N = static_cast<int>(N);
+  ctx->g.Npad = (N + 127) / 128 * 128;
+  ctx->elem = p.storage == LB_F64 ? 8 : (p.storage == LB_F32 ? 4 : 2);
+  ctx->grid_bytes = ctx->elem * static_cast<size_t>(Q) * static_cast<size_t>(ctx->g.Npad);
+  StepCoeffs& c = ctx->c;
+  c.om[0] = c.om[1] = 1.0 / p.tau[0];
+  c.omc[0] = c.omc[1] = 1.0 - c.om[0];
+  c.omf[0] = c.omf[1] = static_cast<float>(c.om[0]);
+  c.omcf[0] = c.omcf[1] = static_cast<float>(c.omc[0]);
+  for (int i = 0; i < Q; ++i)
+    c.shift[0][i] = p.storage == LB_F16_SHIFTED ? static_cast<float>(weight<double>(i) * p.rho0[0]) : 0.0f;
+  lb_status st = LB_OK;
+  for (int b = 0; b < 2 && st == LB_OK; ++b) st = alloc1(&ctx->grid[b], ctx->grid_bytes);
+  if (st == LB_OK) st = alloc1(reinterpret_cast<void**>(&ctx->partial), sizeof(double) * 8 * kTotalsMaxBlocks);
+  if (st == LB_OK) st = alloc1(reinterpret_cast<void**>(&ctx->result), sizeof(double) * 8);
+  if (st == LB_OK) st = alloc1(reinterpret_cast<void**>(&ctx->flag), sizeof(int) * 4);
+  if (st != LB_OK) {
+    free1(ctx);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return LB_OK;
+}
+
+lb_status lb1_destroy(lb1_ctx* ctx) {
+  if (ctx == nullptr) return LB_OK;
+  DeviceGuard dg(ctx->p.device);
+  free1(ctx);
+  delete ctx;
+  return LB_OK;
+}
+
+lb_status lb1_set_stream(lb1_ctx* ctx, void* stream) {
+  if (ctx == nullptr) return LB_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->p.stream = stream;
+  return LB_OK;
+}
+
+lb_status lb1_set_fields(lb1_ctx* ctx, const double* rho, const double* u, const uint8_t* solid, int on_device) {
+  if (ctx == nullptr || rho == nullptr) return LB_EINVAL;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  const double* dr = rho;
+  const double* du = u;
+  void* tmp = nullptr;
+  if (!on_device) {
+    if (hipMalloc(&tmp, sizeof(double) * (u != nullptr ? 4 : 1) * N) != hipSuccess) {
+      (void)hipGetLastError();
+      return LB_ENOMEM;
+    }
+    double* t = static_cast<double*>(tmp);
+    bool ok = hipMemcpyAsync(t, rho, sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (ok && u != nullptr)
+      ok = hipMemcpyAsync(t + N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      (void)hipFree(tmp);
+      return LB_EDEVICE;
+    }
+    dr = t;
+    du = u != nullptr ? t + N : nullptr;
+  }
+  auto finish = [&](lb_status st) {
+    if (tmp != nullptr) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(tmp);
+    }
+    return st;
+  };
+  int bad = 0;
+  if (hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream) != hipSuccess) return finish(LB_EDEVICE);
+  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dr, dr, du, ctx->g.N, ctx->flag);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return finish(LB_EDEVICE);
+  if (bad) return finish(LB_EINVAL);
+  if (solid != nullptr) {
+    if (ctx->mask == nullptr && alloc1(reinterpret_cast<void**>(&ctx->mask), N) != LB_OK) return finish(LB_ENOMEM);
+    if (hipMemcpyAsync(ctx->mask, solid, N, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return finish(LB_EDEVICE);
+    }
+  }
+  ctx->has_solid = solid != nullptr;
+  // solid nodes are never written by a step, so both grids start from zero
+  for (int b = 0; b < 2; ++b)
+    if (hipMemsetAsync(ctx->grid[b], 0, ctx->grid_bytes, ctx->stream) != hipSuccess) return finish(LB_EDEVICE);
+  ctx->cur = 0;
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    k1_init<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        dr, du, m, static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[0]), ctx->g, ctx->c);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+  if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
+  if (st == LB_OK) ctx->has_state = true;
+  return finish(st);
+}
+
+lb_status lb1_step(lb1_ctx* ctx, int32_t n) {
+  if (ctx == nullptr || n < 0) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  if (n == 0) return LB_OK;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  return by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    using store = typename StorageTraits<ST>::store_t;
+    for (int s = 0; s < n; ++s) {
+      const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+      store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+      if (m) k1_step<ST, true><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c);
+      else k1_step<ST, false><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c);
+      LB_HIP(hipGetLastError());
+      ctx->cur ^= 1;
+    }
+    return LB_OK;
+  });
+}
+
+lb_status lb1_moments(lb1_ctx* ctx, double* rho, double* u, int on_device) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  double* dr = rho;
+  double* du = u;
+  void* tmp = nullptr;
+  if (!on_device) {
+    if (hipMalloc(&tmp, sizeof(double) * 4 * N) != hipSuccess) {
+      (void)hipGetLastError();
+      return LB_ENOMEM;
+    }
+    dr = rho ? static_cast<double*>(tmp) : nullptr;
+    du = u ? static_cast<double*>(tmp) + N : nullptr;
+  }
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    k1_moments<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        static_cast<const typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), m, dr, du, ctx->g, ctx->c);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+  bool ok = st == LB_OK;
+  if (ok && !on_device && rho)
+    ok = hipMemcpyAsync(rho, dr, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+  if (ok && !on_device && u)
+    ok = hipMemcpyAsync(u, du, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(ctx->stream) == hipSuccess;
+  (void)hipGetLastError();
+  if (tmp != nullptr) (void)hipFree(tmp);
+  if (st != LB_OK) return st;
+  return ok ? LB_OK : LB_EDEVICE;
+}
+
+lb_status lb1_get_populations(lb1_ctx* ctx, double* f, int on_device) {
+  if (ctx == nullptr || f == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  if (!on_device && ctx->plane == nullptr) {
+    lb_status st = alloc1(reinterpret_cast<void**>(&ctx->plane), sizeof(double) * N);
+    if (st != LB_OK) return st;
+  }
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  for (int plane = 0; plane < Q; ++plane) {
+    double* dst = on_device ? f + plane * N : ctx->plane;
+    lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+      constexpr int ST = decltype(tag)::value;
+      k_decode_plane<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+          static_cast<const typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), dst, m, plane, ctx->g, ctx->c);
+      return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+    });
+    if (st != LB_OK) return st;
+    if (!on_device) {
+      LB_HIP(hipMemcpyAsync(f + plane * N, ctx->plane, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+      LB_HIP(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
+}
+
+lb_status lb1_totals(lb1_ctx* ctx, double out[4], int* nonfinite) {
+  if (ctx == nullptr || out == nullptr) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  int blocks = blocks_for(ctx->g.N);
+  if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
+  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    k_totals_partial<ST, 1><<<blocks, kBlock, 0, ctx->stream>>>(
+        static_cast<const typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), m, ctx->g, ctx->c, ctx->partial);
+    k_totals_final<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, blocks, ctx->result);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+  if (st != LB_OK) return st;
+  double r[8] = {0};
+  LB_HIP(hipMemcpyAsync(r, ctx->result, sizeof(double) * kTotals, hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  out[0] = r[0];
+  out[1] = r[2];
+  out[2] = r[3];
+  out[3] = r[4];
+  const int nf = r[5] != 0.0 ? 1 : 0;
+  if (nonfinite != nullptr) *nonfinite = nf;
+  return nf ? LB_ENONFINITE : LB_OK;
 }
 
 }  // extern "C"

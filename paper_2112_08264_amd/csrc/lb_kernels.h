@@ -278,7 +278,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int ST>
+template <int ST, int NK = 2>  // NK: number of population sets (components)
 __global__ void __launch_bounds__(kBlock) k_totals_partial(const store_t<ST>* __restrict__ f,
                                                            const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c,
                                                            double* __restrict__ partial) {
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(kBlock) k_totals_partial(const store_t<ST>* __
   for (long long n = (long long)blockIdx.x * kBlock + threadIdx.x; n < g.N; n += (long long)gridDim.x * kBlock) {
     if (mask != nullptr && mask[n]) continue;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NK; ++k) {
       double v[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {

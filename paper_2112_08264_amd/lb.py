@@ -82,6 +82,14 @@ _SIGNATURES = [
     ("lb_step_record", ctypes.c_int, [_P, _P]),
     ("lb_adjoint_step_record", ctypes.c_int, [_P, _P]),
     ("lb_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("lb1_create", ctypes.c_int, [ctypes.POINTER(lb_params), ctypes.POINTER(_P)]),
+    ("lb1_destroy", ctypes.c_int, [_P]),
+    ("lb1_set_stream", ctypes.c_int, [_P, _P]),
+    ("lb1_set_fields", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
+    ("lb1_step", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lb1_moments", ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    ("lb1_get_populations", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("lb1_totals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
 ]
@@ -348,6 +356,104 @@ def lb_device_bytes(ctx) -> int:
 # ---------------------------------------------------------------------------
 # Convenience object over one context
 # ---------------------------------------------------------------------------
+# ---- single-fluid step (the paper's case 1) ---------------------------------
+def lb1_create(params: lb_params) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(library().lb1_create(ctypes.byref(params), ctypes.byref(ctx)), "lb1_create")
+    return ctx
+
+
+def lb1_destroy(ctx) -> None:
+    _check(library().lb1_destroy(ctx), "lb1_destroy")
+
+
+def lb1_set_stream(ctx, stream) -> None:
+    _check(library().lb1_set_stream(ctx, stream), "lb1_set_stream")
+
+
+def lb1_set_fields(ctx, n: int, rho, u=None, solid=None) -> None:
+    pr, dr = _ptr(rho, "float64", n, "rho")
+    pu, du = _ptr(u, "float64", 3 * n, "u")
+    ps, ds = _ptr(solid, "uint8", n, "solid")
+    on_dev = _same_side(dr, du if u is not None else None, ds if solid is not None else None)
+    _check(library().lb1_set_fields(ctx, pr, pu, ps, on_dev), "lb1_set_fields")
+
+
+def lb1_step(ctx, nsteps: int) -> None:
+    _check(library().lb1_step(ctx, int(nsteps)), "lb1_step")
+
+
+def lb1_moments(ctx, n: int, rho=None, u=None) -> None:
+    pr, dr = _ptr(rho, "float64", n, "rho")
+    pu, du = _ptr(u, "float64", 3 * n, "u")
+    on_dev = _same_side(dr if rho is not None else None, du if u is not None else None)
+    _check(library().lb1_moments(ctx, pr, pu, on_dev), "lb1_moments")
+
+
+def lb1_get_populations(ctx, n: int, f) -> None:
+    pf, df = _ptr(f, "float64", Q * n, "f")
+    _check(library().lb1_get_populations(ctx, pf, df), "lb1_get_populations")
+
+
+def lb1_totals(ctx) -> Tuple[Tuple[float, ...], bool]:
+    out = (ctypes.c_double * 4)()
+    nf = ctypes.c_int(0)
+    st = library().lb1_totals(ctx, out, ctypes.byref(nf))
+    if st not in (LB_OK, LB_ENONFINITE):
+        _check(st, "lb1_totals")
+    return tuple(out), bool(nf.value)
+
+
+class SingleFluid:
+    """A single-fluid lattice (the paper's case 1) on one GPU: owns an
+    lb1_ctx.  ``shape`` is (nz, ny, nx); arrays as for ``Lattice``."""
+
+    def __init__(self, shape, tau=1.0, storage="f64", rho0=1.0, device: int = 0, stream=None):
+        nz, ny, nx = (int(s) for s in shape)
+        p = lb_params_default()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.tau[0] = float(tau)
+        p.rho0[0] = float(rho0)
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.device = int(device)
+        p.stream = stream if stream is not None else _current_stream(device)
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.ctx = lb1_create(p)
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value is not None:
+            lb1_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_fields(self, rho, u=None, solid=None):
+        lb1_set_fields(self.ctx, self.n, rho, u, solid)
+
+    def step(self, nsteps: int = 1):
+        lb1_step(self.ctx, nsteps)
+
+    def moments(self, rho=None, u=None):
+        lb1_moments(self.ctx, self.n, rho, u)
+
+    def get_populations(self, f):
+        lb1_get_populations(self.ctx, self.n, f)
+
+    def totals(self):
+        return lb1_totals(self.ctx)
+
+
 class Lattice:
     """One lattice on one GPU: owns an lb_ctx and forwards to the C entry points.
 

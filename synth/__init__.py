@@ -62,6 +62,10 @@ WORKLOADS = {
     "spinodal256_f32": Workload("spinodal256_f32", (256, 256, 256), "f32", (0.8, 0.8), 3.5, (1.0, 1.0), 0.02, 1000, 2),
     "spinodal256_f16s": Workload("spinodal256_f16s", (256, 256, 256), "f16s", (0.8, 0.8), 3.5, (1.0, 1.0), 0.02, 1000, 2),
     "adjoint128_f32": Workload("adjoint128_f32", (128, 128, 128), "f32", (1.0, 1.0), 3.5, (1.0, 1.0), 0.02, 500, 3),
+    # single fluid (the paper's case 1: one fluid, fused BGK step, periodic cube); G and the second
+    # component are unused
+    "case1_256_f32": Workload("case1_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 1000, 8),
+    "case1_256_f64": Workload("case1_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 1000, 8),
     "spheres512_f32": Workload("spheres512_f32", (512, 512, 512), "f32", (1.0, 1.0), 3.5, (1.0, 1.0), 0.02, 500, 7,
                                spheres=2000, radius=5.5, sphere_seed=6),
 }

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "lb.h")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lb1?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_loads_and_exports_every_declared_symbol():
@@ -88,3 +88,26 @@ def test_timing_slot_names():
     names = [P.lb_timing_name(i) for i in range(P.lb_timing_slots())]
     assert all(names) and len(set(names)) == len(names)
     assert P.lb_timing_name(P.lb_timing_slots()) is None
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("nz", -1), ("storage", 9)])
+def test_single_fluid_create_rejects_bad_parameters_without_a_device(field, value):
+    p = P.lb_params_default()
+    setattr(p, field, value)
+    ctx = ctypes.c_void_p()
+    assert P.library().lb1_create(ctypes.byref(p), ctypes.byref(ctx)) == P.LB_EINVAL
+    assert ctx.value is None
+
+
+def test_single_fluid_create_rejects_tau_at_or_below_one_half():
+    p = P.lb_params_default()
+    p.tau[0] = 0.5
+    ctx = ctypes.c_void_p()
+    assert P.library().lb1_create(ctypes.byref(p), ctypes.byref(ctx)) == P.LB_EINVAL
+
+
+def test_single_fluid_calls_reject_null_context():
+    lib = P.library()
+    assert lib.lb1_step(None, 1) == P.LB_EINVAL
+    assert lib.lb1_destroy(None) == P.LB_OK
+
