@@ -183,6 +183,39 @@ def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000), restart=(1
     return out
 
 
+def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10):
+    """The single-fluid fused step (the paper's case 1) on 256^3 in float32
+    and float64: GLUPS and the fraction of the HBM roofline at 19 values read
+    and 19 written per node."""
+    out = {"workload": "case1_256", "lattice": [256, 256, 256],
+           "paper_context": "2.011 GLUPS: one fluid, fused step, 256^3, single precision, one V100 (Table 1)"}
+    for st in ("f32", "f64"):
+        w = synth.WORKLOADS[f"case1_256_{st}"]
+        rho, _ = synth.fluid_fields(w.shape, w.amp, w.seed)
+        lat = P.SingleFluid(w.shape, tau=w.tau[0], storage=w.storage, device=0)
+        try:
+            lat.set_fields(rho.reshape(-1))
+            lat.step(warmup)
+            torch.cuda.synchronize()
+            (m0, *_), _ = lat.totals()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lat.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            (m1, *_), nonfinite = lat.totals()
+        finally:
+            lat.close()
+        glups = w.nodes / (ms * 1e-3) / 1e9
+        bpl = 19 * 2 * BYTES_PER_VALUE[st]
+        out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
+                   "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4), "mass_drift": abs(m1 - m0) / m0,
+                   "nonfinite": nonfinite}
+    return out
+
+
 def adjoint_run(P, torch, synth, every: int = 50):
     """Forward (with checkpoint saves) and backward (recompute + adjoint) of
     J = sum (rho_A(T) - target)^2 on the 128^3 float32 gradient workload."""
@@ -358,6 +391,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-fluid (case 1) timing")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reduced-precision error report")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass", "fused_staged"])
     ap.add_argument("--calibrate", action="store_true",
@@ -447,6 +481,12 @@ def main(argv=None) -> int:
         adjoint = adjoint_run(P, torch, synth)
         log(f"bench: adjoint {adjoint}")
 
+    single = None
+    if not args.no_single:
+        log("bench: single fluid (case 1) 256^3, float32 and float64")
+        single = single_fluid_run(P, torch, synth)
+        log(f"bench: single fluid {single}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -476,6 +516,7 @@ def main(argv=None) -> int:
         "f64_one_ulp_sensitivity": None if accuracy is None else accuracy["f64_one_ulp"],
         "adjoint_forward_ratio": None if adjoint is None else adjoint["ratio"],
         "adjoint": adjoint,
+        "single_fluid": single,
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),
