@@ -23,6 +23,7 @@ __all__ = [
     "Workload",
     "WORKLOADS",
     "fluid_fields",
+    "colour_fields",
     "sphere_centres",
     "solid_mask",
     "smooth_target",
@@ -46,6 +47,8 @@ class Workload:
     spheres: int = 0
     radius: float = 0.0
     sphere_seed: Optional[int] = None
+    sigma: float = 0.0                   # colour-gradient workloads: surface tension
+    beta: float = 0.0                    # colour-gradient workloads: recolouring parameter
 
     @property
     def nodes(self) -> int:
@@ -53,9 +56,10 @@ class Workload:
         return nx * ny * nz
 
 
-# The five workloads: a small box the oracle runs in seconds, the 256^3
+# The Shan-Chen workloads: a small box the oracle runs in seconds, the 256^3
 # spinodal throughput box (FP64, then FP32 / FP16-shifted storage), the
-# 128^3 gradient box, and the 512^3 box with 2000 fixed spheres.
+# 128^3 gradient box, and the 512^3 box with 2000 fixed spheres; then the
+# single-fluid and colour-gradient boxes of the paper's cases 1 and 2.
 WORKLOADS = {
     "mix32_f64": Workload("mix32_f64", (32, 32, 32), "f64", (1.0, 1.0), 3.5, (1.0, 1.0), 0.01, 200, 1),
     "spinodal256_f64": Workload("spinodal256_f64", (256, 256, 256), "f64", (0.8, 0.8), 3.5, (1.0, 1.0), 0.02, 1000, 2),
@@ -68,6 +72,15 @@ WORKLOADS = {
     "case1_256_f64": Workload("case1_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 1000, 8),
     "spheres512_f32": Workload("spheres512_f32", (512, 512, 512), "f32", (1.0, 1.0), 3.5, (1.0, 1.0), 0.02, 500, 7,
                                spheres=2000, radius=5.5, sphere_seed=6),
+    # two immiscible fluids, colour-gradient model (the paper's case 2: every node pure red or pure
+    # blue at random, at rest, periodic cube); tau of both pure fluids, surface tension sigma and
+    # recolouring beta are not given by the paper; G, rho0 and amp are unused
+    "case2_32_f64": Workload("case2_32_f64", (32, 32, 32), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 200, 9,
+                             sigma=0.01, beta=0.7),
+    "case2_256_f32": Workload("case2_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 1000, 10,
+                              sigma=0.01, beta=0.7),
+    "case2_256_f64": Workload("case2_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 1000, 10,
+                              sigma=0.01, beta=0.7),
 }
 
 
@@ -82,6 +95,19 @@ def fluid_fields(shape, amp: float, seed: int, rho0=(1.0, 1.0)):
     a = rho0[0] + rng.uniform(-amp, amp, size=shape)
     b = rho0[1] + rng.uniform(-amp, amp, size=shape)
     return np.ascontiguousarray(a, dtype=np.float64), np.ascontiguousarray(b, dtype=np.float64)
+
+
+def colour_fields(shape, seed: int):
+    """Initial densities of the colour-gradient workloads: each node is pure
+    red (rho_r = 1, rho_b = 0) or pure blue (0, 1) with probability 1/2.
+
+    One ``numpy.random.default_rng(seed)`` stream, one uniform draw per node in
+    C order over ``shape``; red where the draw is below 1/2.
+    """
+    rng = np.random.default_rng(seed)
+    red = rng.random(tuple(int(s) for s in shape)) < 0.5
+    r = np.where(red, 1.0, 0.0)
+    return np.ascontiguousarray(r, dtype=np.float64), np.ascontiguousarray(1.0 - r, dtype=np.float64)
 
 
 def _min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:

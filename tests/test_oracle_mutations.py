@@ -53,6 +53,25 @@ SINGLE = [
     ("single: relaxation weights swapped", "fs = (1.0 - om) * f + om * feq", "fs = (1.0 - om) * feq + om * f"),
 ]
 
+COLOUR = [
+    ("cg: omega as printed, 2/(6 nu - 1)", "return 2.0 / (6.0 * nubar + 1.0)", "return 2.0 / (6.0 * nubar - 1.0)"),
+    ("cg: perturbation without the 1/2", "pcoef = (0.5 * A) * gn", "pcoef = A * gn"),
+    ("cg: axis B_i 1/54 -> 1/27", "[1.0 / 54.0] * 6", "[1.0 / 27.0] * 6"),
+    ("cg: recolouring adds to both components", "out[1, i] = c2 * fstar[i] - t", "out[1, i] = c2 * fstar[i] + t"),
+    ("cg: cos(phi) without |c_i|", "t = (r * (cn[i] / CLEN[i])) * (W[i] * rho)", "t = (r * cn[i]) * (W[i] * rho)"),
+    ("cg: recolouring over rho, not rho^2", "r = (beta * (rho1 * rho2)) / (rho * rho)",
+     "r = (beta * (rho1 * rho2)) / rho"),
+    ("cg: gradient without 1/c_s^2", "return tuple(3.0 * S[a] for a in range(3))", "return tuple(S[a] for a in range(3))"),
+    ("cg: arithmetic mean of the viscosities",
+     "inv_nubar = (rho1 / rho) * inv[0] + (rho2 / rho) * inv[1]\n    nubar = 1.0 / inv_nubar",
+     "nubar = (rho1 / rho) / inv[0] + (rho2 / rho) / inv[1]"),
+    ("cg: phase field sign", "theta = (rho1 - rho2) / rho", "theta = (rho2 - rho1) / rho"),
+    ("cg: velocity of one component", "u = tuple((m1[a] + m2[a]) / rho for a in range(3))",
+     "u = tuple(m1[a] / rho for a in range(3))"),
+    ("cg: no interface cut", "pos = gg > INTERFACE_G2", "pos = gg > 0.0"),
+    ("cg: A without omega", "A = (2.25 * p.sigma) * omega", "A = 2.25 * p.sigma"),
+]
+
 RUNNER = r"""
 import importlib.util, sys
 sys.path.insert(0, {root!r})
@@ -98,6 +117,13 @@ def test_adjoint_pins_catch_planted_mistake(name, old, new):
 def test_single_fluid_pins_catch_planted_mistake(name, old, new):
     tests = [os.path.join(TESTS, "test_oracle_single.py")]
     rc = _run_mutant("lb_single.py", "oracle.lb_single", "lb_single", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
+@pytest.mark.parametrize("name,old,new", COLOUR, ids=[m[0] for m in COLOUR])
+def test_colour_gradient_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_cg.py")]
+    rc = _run_mutant("lb_cg.py", "oracle.lb_cg", "lb_cg", old, new, tests)
     assert rc != 0, f"no pin failed for planted mistake: {name}"
 
 
