@@ -166,6 +166,40 @@ lb_status lb_set_kernel(lb_ctx* ctx, int32_t kernel);
  * Errors: LB_EINVAL (NULL, non-finite G). */
 lb_status lb_set_coupling(lb_ctx* ctx, double G);
 
+/* ---- Colour-gradient model (the paper's two-component model, Appendix;
+ * case 2 of Sec. 5) ----------------------------------------------------------
+ * lb_set_model switches the context's collision between
+ *   LB_MODEL_SHAN_CHEN (the default): the pseudopotential force by velocity
+ *     shift, as described at lb_create;
+ *   LB_MODEL_COLOUR_GRADIENT: per component, BGK towards f^eq(rho_k, u) at
+ *     the mixture velocity u = (m_A + m_B) / rho with one effective
+ *     omega = 2 / (6 nu_bar + 1), 1/nu_bar = (rho_A/rho)/nu_A +
+ *     (rho_B/rho)/nu_B, nu_k = (tau_k - 1/2)/3 (Appendix, Eq. 1coll; Eq. 2),
+ *     plus the perturbation (A/2)|g|(w_i (c_i.n)^2 - B_i) with
+ *     A = (9/4) sigma omega (Eq. 2coll, Eq. sigmaA); the sum of the two
+ *     components is then split by the recolouring
+ *     f_i^A = (rho_A/rho) f*_i + beta (rho_A rho_B / rho^2) cos(phi_i) w_i rho
+ *     and f_i^B = (rho_B/rho) f*_i - (the same term) (Eq. 3coll), where
+ *     g = 3 sum_i w_i Theta(x + c_i) c_i is the gradient of the phase field
+ *     Theta = (rho_A - rho_B)/(rho_A + rho_B), n = g/|g| and
+ *     cos(phi_i) = c_i.n / |c_i|.  The perturbation and the recolouring act
+ *     only where |g|^2 > 1e-16 (float32: 1e-10).  Streaming is periodic.
+ * sigma (surface tension, >= 0) and beta (recolouring, >= 0) are used by the
+ * colour-gradient model only; G and psi_ref by the Shan-Chen model only.
+ * The model applies to later lb_step calls; lb_moments then reports
+ * u = (m_A + m_B) / rho.  The colour-gradient model takes LB_F64 or LB_F32
+ * storage, no solid nodes, and every node needs rho_A + rho_B > 0
+ * (lb_set_fields checks this); lb_step with LB_KERNEL_TWO_PASS, the
+ * adjoint calls, lb_step_record and lb_step_between return LB_EINVAL in it.
+ * Errors: LB_EINVAL (NULL ctx, unknown model, non-finite or negative sigma
+ * or beta, LB_F16_SHIFTED storage or solid nodes with the colour-gradient
+ * model). */
+typedef enum {
+  LB_MODEL_SHAN_CHEN = 0,
+  LB_MODEL_COLOUR_GRADIENT = 1
+} lb_model;
+lb_status lb_set_model(lb_ctx* ctx, int32_t model, double sigma, double beta);
+
 /* ---- Raw state snapshots (checkpointing) -------------------------------
  * A snapshot is the current population grid in the library's own storage
  * layout: lb_state_bytes() bytes, structure of arrays in the context's

@@ -85,6 +85,7 @@ struct lb_ctx {
   double* adj_dG = nullptr;           // running dJ/dG
   bool adj_ready = false;
   int kernel = LB_KERNEL_FUSED_STAGED;  // LB_KERNEL_AUTO
+  int model = LB_MODEL_SHAN_CHEN;
   FusedTiling tiling{};       // the storage's default fused kernel
   FusedTiling tiling_wide{};  // staged float64 kernel on 64 x 4 tiles (nx a multiple of 64)
   int64_t bytes = 0;
@@ -233,9 +234,45 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
   }
 }
 
+// Colour-gradient step from fin to fout: the component-pair kernel with the
+// colour-gradient collision.  float64 runs staged where the Shan-Chen step
+// would (same tiles and tiling); float32 runs unstaged on 64 x 4 tiles (the
+// float storages' tiling).
+template <int ST>
+void launch_cg_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
+                  typename StorageTraits<ST>::store_t* fout) {
+  if constexpr (ST == ST_F64) {
+    if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx)) {
+      const FusedTiling t = ctx->tiling_wide;
+      k_fused_pair<ST, false, kWideTY, false, true, kWideTX, kModelCG>
+          <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                             nullptr);
+      return;
+    }
+    const FusedTiling t = ctx->tiling;
+    if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_fits(ctx)) {
+      k_fused_pair<ST, false, kFusedTY, false, true, kFusedTX, kModelCG>
+          <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr);
+      return;
+    }
+    k_fused_pair<ST, false, kFusedTY, false, false, kFusedTX, kModelCG>
+        <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr);
+  } else if constexpr (ST == ST_F32) {
+    const FusedTiling t = ctx->tiling;
+    k_fused_pair<ST, false, kFloatTY, false, false, kFloatTX, kModelCG>
+        <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                             nullptr);
+  }
+}
+
 template <int ST>
 lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
                        typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
+  if (ctx->model == LB_MODEL_COLOUR_GRADIENT) {
+    // lb_set_model admits float64 and float32 storage without solids only
+    if (ST == ST_F16S || ctx->has_solid || rec != nullptr) return LB_EINVAL;
+    return launch(ctx, SLOT_FUSED, [&] { launch_cg_as<ST>(ctx, fin, fout); });
+  }
   const bool solid = ctx->has_solid;
   return launch(ctx, SLOT_FUSED, [&] {
     if (solid) {
@@ -270,6 +307,7 @@ bool use_fused(const lb_ctx* ctx) {
 template <int ST>
 lb_status step_impl(lb_ctx* ctx, int n) {
   if (use_fused(ctx)) return fused_step_impl<ST>(ctx, n);
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // the colour-gradient step is fused only
   using store = typename StorageTraits<ST>::store_t;
   using real = typename StorageTraits<ST>::real;
   const int nb = blocks_for(ctx->g.N);
@@ -336,12 +374,19 @@ lb_status moments_impl(lb_ctx* ctx, double* ra, double* rb, double* u) {
   const store* f = static_cast<const store*>(ctx->grid[ctx->cur]);
   real* psi = static_cast<real*>(ctx->psi);
   const int nb = blocks_for(ctx->g.N);
+  // The colour-gradient velocity has no force term: with G = 0 the kernel's
+  // (m_A + m_B + (F_A + F_B) / 2) / rho adds an exact zero.
+  StepCoeffs c = ctx->c;
+  if (ctx->model == LB_MODEL_COLOUR_GRADIENT) {
+    c.G = 0.0;
+    c.Gf = 0.0f;
+  }
   if (ctx->has_solid) {
-    k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, ctx->c);
-    k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, ctx->c);
+    k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, c);
+    k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, c);
   } else {
-    k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, ctx->c);
-    k_moments<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, ctx->c);
+    k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, c);
+    k_moments<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, c);
   }
   LB_HIP(hipGetLastError());
   return LB_OK;
@@ -743,6 +788,7 @@ lb_status lb_device_bytes(const lb_ctx* ctx, int64_t* bytes) {
 lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b, const double* u,
                         const uint8_t* solid, int on_device) {
   if (ctx == nullptr || rho_a == nullptr || rho_b == nullptr) return LB_EINVAL;
+  if (solid != nullptr && ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
   const size_t N = static_cast<size_t>(ctx->g.N);
@@ -782,7 +828,8 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b, c
     release();
     return LB_EDEVICE;
   }
-  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dra, drb, du, ctx->g.N, ctx->flag);
+  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dra, drb, du, ctx->g.N, ctx->flag,
+                                                                      ctx->model == LB_MODEL_COLOUR_GRADIENT);
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -937,6 +984,24 @@ lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite) {
   return nf ? LB_ENONFINITE : LB_OK;
 }
 
+lb_status lb_set_model(lb_ctx* ctx, int32_t model, double sigma, double beta) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (model != LB_MODEL_SHAN_CHEN && model != LB_MODEL_COLOUR_GRADIENT) return LB_EINVAL;
+  if (!is_finite(sigma) || !is_finite(beta) || sigma < 0.0 || beta < 0.0) return LB_EINVAL;
+  if (model == LB_MODEL_COLOUR_GRADIENT && (ctx->p.storage == LB_F16_SHIFTED || ctx->has_solid)) return LB_EINVAL;
+  StepCoeffs& c = ctx->c;
+  for (int k = 0; k < 2; ++k) {
+    c.cg_inv_nu[k] = 1.0 / ((ctx->p.tau[k] - 0.5) / 3.0);
+    c.cg_inv_nuf[k] = static_cast<float>(c.cg_inv_nu[k]);
+  }
+  c.cg_s225 = 2.25 * sigma;
+  c.cg_beta = beta;
+  c.cg_s225f = static_cast<float>(c.cg_s225);
+  c.cg_betaf = static_cast<float>(beta);
+  ctx->model = model;
+  return LB_OK;
+}
+
 lb_status lb_set_coupling(lb_ctx* ctx, double G) {
   if (ctx == nullptr || !is_finite(G)) return LB_EINVAL;
   ctx->p.G = G;
@@ -980,6 +1045,7 @@ lb_status lb_restore_state(lb_ctx* ctx, const void* src, int on_device) {
 
 lb_status lb_step_between(lb_ctx* ctx, const void* fin, void* fout) {
   if (ctx == nullptr || fin == nullptr || fout == nullptr || fin == fout) return LB_EINVAL;
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // Shan-Chen only
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
   return by_storage(ctx, [&](auto tag) { return step_between_impl<decltype(tag)::value>(ctx, fin, fout); });
@@ -993,6 +1059,7 @@ lb_status lb_record_bytes(const lb_ctx* ctx, int64_t* bytes) {
 
 lb_status lb_step_record(lb_ctx* ctx, void* record) {
   if (ctx == nullptr || record == nullptr) return LB_EINVAL;
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // Shan-Chen only
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
@@ -1001,6 +1068,7 @@ lb_status lb_step_record(lb_ctx* ctx, void* record) {
 
 lb_status lb_adjoint_step_record(lb_ctx* ctx, const void* record) {
   if (ctx == nullptr || record == nullptr) return LB_EINVAL;
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // Shan-Chen only
   if (!ctx->adj_ready) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
@@ -1012,6 +1080,7 @@ lb_status lb_adjoint_step_record(lb_ctx* ctx, const void* record) {
 
 lb_status lb_adjoint_begin(lb_ctx* ctx, const double* dJ_drho_a, const double* dJ_drho_b, int on_device) {
   if (ctx == nullptr) return LB_EINVAL;
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // Shan-Chen only
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
   const size_t N = static_cast<size_t>(ctx->g.N);
@@ -1043,6 +1112,7 @@ lb_status lb_adjoint_begin(lb_ctx* ctx, const double* dJ_drho_a, const double* d
 
 lb_status lb_adjoint_step(lb_ctx* ctx, const void* state) {
   if (ctx == nullptr || state == nullptr) return LB_EINVAL;
+  if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // Shan-Chen only
   if (!ctx->adj_ready) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
@@ -1240,7 +1310,7 @@ lb_status lb1_set_fields(lb1_ctx* ctx, const double* rho, const double* u, const
   };
   int bad = 0;
   if (hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream) != hipSuccess) return finish(LB_EDEVICE);
-  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dr, dr, du, ctx->g.N, ctx->flag);
+  k_validate_fields<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(dr, dr, du, ctx->g.N, ctx->flag, 0);
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)

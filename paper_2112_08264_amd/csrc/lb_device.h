@@ -1,6 +1,7 @@
-// Device-side building blocks of the two-component D3Q19 Shan-Chen step:
-// lattice constants, the pseudopotential's exp, population storage codecs
-// and the per-node collision shared by every step kernel.
+// Device-side building blocks of the two-component D3Q19 steps (Shan-Chen,
+// and the colour-gradient constants): lattice constants, the
+// pseudopotential's exp, population storage codecs and the per-node
+// Shan-Chen collision shared by its step kernels.
 //
 // Floating-point order.  The float64 path performs the same IEEE operations
 // in the same order as the published definition below, with no fused
@@ -60,6 +61,10 @@ struct StepCoeffs {
   double psi_ref;
   float omf[2], omcf[2], tgf[2], tauf[2], Gf, psi_reff;
   float shift[2][Q];  // w_i * rho0_k, the float16 storage offset
+  // colour-gradient model: 1/nu_k = 1 / ((tau_k - 1/2) / 3), 2.25 sigma (so
+  // that A = (2.25 sigma) omega), beta
+  double cg_inv_nu[2], cg_s225, cg_beta;
+  float cg_inv_nuf[2], cg_s225f, cg_betaf;
 };
 
 struct Geometry {
@@ -143,6 +148,36 @@ template <> __device__ __forceinline__ float coef_G<float>(const StepCoeffs& c) 
 template <typename real> __device__ __forceinline__ real coef_ref(const StepCoeffs& c);
 template <> __device__ __forceinline__ double coef_ref<double>(const StepCoeffs& c) { return c.psi_ref; }
 template <> __device__ __forceinline__ float coef_ref<float>(const StepCoeffs& c) { return c.psi_reff; }
+
+template <typename real> __device__ __forceinline__ real coef_cg_inv_nu(const StepCoeffs& c, int k);
+template <> __device__ __forceinline__ double coef_cg_inv_nu<double>(const StepCoeffs& c, int k) { return c.cg_inv_nu[k]; }
+template <> __device__ __forceinline__ float coef_cg_inv_nu<float>(const StepCoeffs& c, int k) { return c.cg_inv_nuf[k]; }
+template <typename real> __device__ __forceinline__ real coef_cg_s225(const StepCoeffs& c);
+template <> __device__ __forceinline__ double coef_cg_s225<double>(const StepCoeffs& c) { return c.cg_s225; }
+template <> __device__ __forceinline__ float coef_cg_s225<float>(const StepCoeffs& c) { return c.cg_s225f; }
+template <typename real> __device__ __forceinline__ real coef_cg_beta(const StepCoeffs& c);
+template <> __device__ __forceinline__ double coef_cg_beta<double>(const StepCoeffs& c) { return c.cg_beta; }
+template <> __device__ __forceinline__ float coef_cg_beta<float>(const StepCoeffs& c) { return c.cg_betaf; }
+
+// ---------------------------------------------------------------------------
+// Colour-gradient constants (Appendix): the perturbation coefficients B_i by
+// |c|^2 class from the Appendix table, |c_i| (1 at rest, where c_i . n = 0),
+// and the squared phase-field gradient above which a node counts as
+// interface: the perturbation and the recolouring act there only.  float64
+// cuts at |grad Theta| = 1e-8, well above its rounding noise in a uniform
+// mixture (~1e-16); float arithmetic at 1e-5, above its own (~1e-7).
+// ---------------------------------------------------------------------------
+template <typename T>
+__host__ __device__ constexpr T cg_b(int i) {
+  return i == 0 ? T(-2) / T(9) : (i <= 6 ? T(1) / T(54) : T(1) / T(27));
+}
+template <typename T>
+__host__ __device__ constexpr T cg_clen(int i) {
+  return i <= 6 ? T(1) : T(1.4142135623730951);
+}
+template <typename T> __host__ __device__ constexpr T cg_interface_g2();
+template <> __host__ __device__ constexpr double cg_interface_g2<double>() { return 1e-16; }
+template <> __host__ __device__ constexpr float cg_interface_g2<float>() { return 1e-10f; }
 
 // ---------------------------------------------------------------------------
 // Local moments of one component's 19 populations.

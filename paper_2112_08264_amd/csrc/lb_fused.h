@@ -42,6 +42,9 @@ namespace lbd {
 
 constexpr int kFusedTX = 32;
 constexpr int kXCDs = 8;
+// collision model of the component-pair kernel
+constexpr int kModelSC = 0;  // Shan-Chen pseudopotential force, velocity shift
+constexpr int kModelCG = 1;  // colour gradient: BGK + perturbation + recolouring
 
 // Workgroup barrier that orders LDS accesses only.  The waves of a fused
 // workgroup exchange data through LDS alone (the kernels never read what
@@ -305,12 +308,15 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 }
 
 // ---------------------------------------------------------------------------
-// Component-pair variant (used for float64).  Each wave holds 32 nodes of
-// one tile row for both components: lanes 0..31 carry component A, lanes
-// 32..63 component B of the same nodes, and the partner lane (lane ^ 32)
-// supplies the other component's density and momentum by a lane shuffle.
-// A tile row of TX = 32 or 64 nodes takes TX / 32 waves.  Ring of three psi
-// planes.
+// Component-pair variant (float64 Shan-Chen; every colour-gradient step).
+// Each wave holds 32 nodes of one tile row for both components: lanes 0..31
+// carry component A, lanes 32..63 component B of the same nodes, and the
+// partner lane (lane ^ 32) supplies the other component's density and
+// momentum by a lane shuffle.  A tile row of TX = 32 or 64 nodes takes
+// TX / 32 waves.  Ring of three planes of the stencil field: psi of both
+// components (MODEL = kModelSC) or the phase field (kModelCG, whose
+// recolouring also needs the partner's 19 post-perturbation populations,
+// one shuffle each).
 //
 // STAGED = false: no prefetch.  The plane z + 1 loads go to registers and
 // are consumed in the same iteration, which keeps the float64 register
@@ -329,7 +335,7 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 // rows x TX nodes + 2 (TY + 2) side nodes) float64: 120,384 bytes for
 // 64 x 4 tiles, 103,360 for 32 x 8, so one workgroup per compute unit.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX>
+template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC>
 __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                             store_t<ST>* __restrict__ fout,
                                                             const uint8_t* __restrict__ mask, Geometry g,
@@ -346,6 +352,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   // With solids the staged variant needs more than the 256 registers two
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
+  static_assert(MODEL == kModelSC || (!SOLID && !RECORD), "the colour-gradient step has no solids and no adjoint record");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -441,22 +448,33 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     }
   };
 
-  auto psi_of = [&](long long n, long long kp, int kk, bool solid, real (&v)[Q]) -> real {
+  auto rho_of = [&](long long n, long long kp, int kk, real (&v)[Q]) -> real {
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = decode<ST>(fin[kp + (long long)i * g.Npad + n], c.shift[kk][i]);
-    if (SOLID && solid) return real(0);
-    return pseudopotential(density<real>(v), coef_ref<real>(c));
+    return density<real>(v);
+  };
+  // Ring entry of a node from its density rho_kk.  Shan-Chen: psi_kk (0 at
+  // solid nodes).  Colour gradient: the phase field
+  // Theta = (rho_A - rho_B) / (rho_A + rho_B), written by the component-A
+  // lane; the lane holding component B of the same node is lane ^ pm, and
+  // both lanes must reach this call.
+  auto ring_put = [&](int s, int kk, int y, int x, real rho, bool solid, int pm) {
+    if constexpr (MODEL == kModelSC) {
+      ring[s][kk][y][x] = (SOLID && solid) ? real(0) : pseudopotential(rho, coef_ref<real>(c));
+    } else {
+      const real o = __shfl_xor(rho, pm, 64);
+      if (kk == 0) ring[s][0][y][x] = (rho - o) / (rho + o);
+    }
   };
 
-  // ring slot s <- psi of plane z; interior lanes keep their populations in `keep`
+  // ring slot s <- plane z; interior lanes keep their populations in `keep`
   auto fill = [&](int s, int z, real (&keep)[Q]) {
     const long long zoff = plane_n * z;
     {
       const long long n = row + zoff;
       bool solid = false;
       if constexpr (SOLID) solid = mask[n] != 0;
-      const real p = psi_of(n, kplane, k, solid, keep);
-      ring[s][k][ly + 1][lx + 1] = p;
+      ring_put(s, k, ly + 1, lx + 1, rho_of(n, kplane, k, keep), solid, 32);
       if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid;
     }
     if (has_halo) {
@@ -464,8 +482,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       bool solid = false;
       if constexpr (SOLID) solid = mask[n] != 0;
       real tmp[Q];
-      const real p = psi_of(n, hkplane, hk, solid, tmp);
-      ring[s][hk][hy + 1][hx + 1] = p;
+      ring_put(s, hk, hy + 1, hx + 1, rho_of(n, hkplane, hk, tmp), solid, 1);
       if constexpr (SOLID) if (hk == 0) ring_solid[s][hy + 1][hx + 1] = solid;
     }
   };
@@ -508,11 +525,14 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       const real mA = k == 0 ? m_k[a] : m_o[a], mB = k == 0 ? m_o[a] : m_k[a];
       up[a] = (omA * mA + omB * mB) / den;
     }
+    // S = sum_i w_i q(x + c_i) c_i, q = psi of the other component
+    // (Shan-Chen) or the phase field (colour gradient)
+    constexpr bool SC = MODEL == kModelSC;
     real S[3] = {real(0), real(0), real(0)};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-      const real tt = weight<real>(i) * ring[si][1 - k][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      const real tt = weight<real>(i) * ring[si][SC ? 1 - k : 0][ly + 1 + CY[i]][lx + 1 + CX[i]];
       if (CX[i] == 1) S[0] = S[0] + tt;
       if (CX[i] == -1) S[0] = S[0] - tt;
       if (CY[i] == 1) S[1] = S[1] + tt;
@@ -562,16 +582,58 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     };
     if (active && !here_solid) {
       real fs[Q];
+      if constexpr (SC) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const real cu = cdot<real>(i, vx, vy, vz);
-        const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
-        fs[i] = omck * cur[i] + omk * feq;
-        if constexpr (SOLID) {
-          if (i != 0) {
-            const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-            if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) bounced |= 1u << i;
+        for (int i = 0; i < Q; ++i) {
+          const real cu = cdot<real>(i, vx, vy, vz);
+          const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+          fs[i] = omck * cur[i] + omk * feq;
+          if constexpr (SOLID) {
+            if (i != 0) {
+              const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+              if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) bounced |= 1u << i;
+            }
           }
+        }
+      } else {
+        // Colour gradient (Appendix): BGK with the mean-viscosity omega plus
+        // the perturbation, per component; the two summed into f*; f* split
+        // between the components by the recolouring.  The partner lane
+        // (lane ^ 32, same node, other component) is active exactly when
+        // this lane is, so the exchanges below are complete.
+        const real rho = rhoA + rhoB;
+        real u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const real mA = k == 0 ? m_k[a] : m_o[a], mB = k == 0 ? m_o[a] : m_k[a];
+          u[a] = (mA + mB) / rho;
+        }
+        const real g3[3] = {real(3) * S[0], real(3) * S[1], real(3) * S[2]};
+        const real gg = (g3[0] * g3[0] + g3[1] * g3[1]) + g3[2] * g3[2];
+        const bool iface = gg > cg_interface_g2<real>();
+        const real gn = iface ? real(sqrt(gg)) : real(0);
+        real nv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nv[a] = iface ? g3[a] / gn : real(0);
+        const real inv_nubar = (rhoA / rho) * coef_cg_inv_nu<real>(c, 0) + (rhoB / rho) * coef_cg_inv_nu<real>(c, 1);
+        const real nubar = real(1) / inv_nubar;
+        const real om = real(2) / (real(6) * nubar + real(1));
+        const real pcoef = (real(0.5) * (coef_cg_s225<real>(c) * om)) * gn;
+        const real r = (coef_cg_beta<real>(c) * (rhoA * rhoB)) / (rho * rho);
+        const real ck = rho_k / rho;
+        const real uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+        const real t15u = real(1.5) * uu;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const real cu = cdot<real>(i, u[0], u[1], u[2]);
+          const real feq = (weight<real>(i) * rho_k) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15u);
+          const real cn = cdot<real>(i, nv[0], nv[1], nv[2]);
+          const real pert = pcoef * (weight<real>(i) * (cn * cn) - cg_b<real>(i));
+          const real fk = (cur[i] + om * (feq - cur[i])) + pert;
+          const real fo = __shfl_xor(fk, 32, 64);
+          const real fstar = k == 0 ? fk + fo : fo + fk;
+          const real t = (r * (cn / cg_clen<real>(i))) * (weight<real>(i) * rho);
+          fs[i] = k == 0 ? ck * fstar + t : ck * fstar - t;
         }
       }
       if constexpr (STAGED) {
@@ -596,7 +658,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
 #pragma unroll
             for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * 2 * RY];
           }
-          ring[sm][hk][hy + 1][hx + 1] = pseudopotential(density<real>(h), coef_ref<real>(c));
+          ring_put(sm, hk, hy + 1, hx + 1, density<real>(h), false, 1);
         }
         if (store) push(cur, bounced);
 #pragma unroll
@@ -604,7 +666,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
           cur[i] = nxt[i];
           nxt[i] = stage[ibase + i * RY * TX];
         }
-        ring[sm][k][ly + 1][lx + 1] = pseudopotential(density<real>(nxt), coef_ref<real>(c));
+        ring_put(sm, k, ly + 1, lx + 1, density<real>(nxt), false, 32);
       } else {
         if (store) push(cur, bounced);
 #pragma unroll

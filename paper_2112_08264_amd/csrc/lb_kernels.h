@@ -153,10 +153,12 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ ra, 
 // Reject non-finite or negative densities and non-finite velocities.
 __global__ void __launch_bounds__(kBlock) k_validate_fields(const double* __restrict__ ra,
                                                             const double* __restrict__ rb,
-                                                            const double* __restrict__ u, int N, int* flag) {
+                                                            const double* __restrict__ u, int N, int* flag,
+                                                            int need_total) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= N) return;
   bool bad = !(ra[n] >= 0.0 && ra[n] <= 1.0e300) || !(rb[n] >= 0.0 && rb[n] <= 1.0e300);
+  if (need_total) bad = bad || !(ra[n] + rb[n] > 0.0);  // the phase field needs rho_A + rho_B > 0
   if (u != nullptr) {
     for (int a = 0; a < 3; ++a) {
       const double v = u[(long long)a * N + n];

@@ -22,6 +22,8 @@ LB_KERNEL_AUTO, LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS, LB_KERNEL_FUSED_STAGED = 0,
 KERNELS = {"auto": LB_KERNEL_AUTO, "fused": LB_KERNEL_FUSED, "two_pass": LB_KERNEL_TWO_PASS,
            "fused_staged": LB_KERNEL_FUSED_STAGED}
 STORAGE = {"f64": LB_F64, "f32": LB_F32, "f16s": LB_F16_SHIFTED}
+LB_MODEL_SHAN_CHEN, LB_MODEL_COLOUR_GRADIENT = 0, 1
+MODELS = {"shan_chen": LB_MODEL_SHAN_CHEN, "colour_gradient": LB_MODEL_COLOUR_GRADIENT}
 Q = 19
 
 
@@ -70,6 +72,7 @@ _SIGNATURES = [
     ("lb_timing_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("lb_set_kernel", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lb_set_coupling", ctypes.c_int, [_P, ctypes.c_double]),
+    ("lb_set_model", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double]),
     ("lb_state_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     ("lb_save_state", ctypes.c_int, [_P, _P, ctypes.c_int]),
     ("lb_restore_state", ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -259,6 +262,11 @@ def lb_set_kernel(ctx, kernel) -> None:
 
 def lb_set_coupling(ctx, G: float) -> None:
     _check(library().lb_set_coupling(ctx, float(G)), "lb_set_coupling")
+
+
+def lb_set_model(ctx, model, sigma: float = 0.0, beta: float = 0.0) -> None:
+    m = MODELS[model] if isinstance(model, str) else int(model)
+    _check(library().lb_set_model(ctx, m, float(sigma), float(beta)), "lb_set_model")
 
 
 def lb_state_bytes(ctx) -> int:
@@ -462,7 +470,7 @@ class Lattice:
     """
 
     def __init__(self, shape, tau=(1.0, 1.0), G=0.0, psi_ref=1.0, storage="f64", rho0=(1.0, 1.0),
-                 device: int = 0, stream=None, kernel="auto"):
+                 device: int = 0, stream=None, kernel="auto", model="shan_chen", sigma=0.0, beta=0.0):
         nz, ny, nx = (int(s) for s in shape)
         p = lb_params_default()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -477,7 +485,12 @@ class Lattice:
         self.n = nx * ny * nz
         self.params = p
         self.ctx = lb_create(p)
-        lb_set_kernel(self.ctx, kernel)
+        try:
+            lb_set_kernel(self.ctx, kernel)
+            lb_set_model(self.ctx, model, sigma, beta)
+        except Exception:
+            self.close()
+            raise
 
     def close(self):
         if self.ctx is not None and self.ctx.value is not None:

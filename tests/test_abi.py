@@ -75,6 +75,7 @@ def test_null_arguments_are_rejected():
     assert lib.lb_totals(None, None, None) == P.LB_EINVAL
     assert lib.lb_get_populations(None, None, 0) == P.LB_EINVAL
     assert lib.lb_set_populations(None, None, 0) == P.LB_EINVAL
+    assert lib.lb_set_model(None, P.LB_MODEL_COLOUR_GRADIENT, 0.01, 0.7) == P.LB_EINVAL
     assert lib.lb_destroy(None) == P.LB_OK
 
 
