@@ -216,6 +216,41 @@ def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10):
     return out
 
 
+def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10):
+    """The colour-gradient step (the paper's case 2, two immiscible fluids) on
+    256^3 in float32 and float64: GLUPS and the fraction of the HBM roofline
+    at 38 values read and 38 written per node."""
+    out = {"workload": "case2_256", "lattice": [256, 256, 256],
+           "paper_context": "0.601 GLUPS: colour gradient, two-pass step, 256^3, single precision, one V100 (Sec. 5, "
+                            "two-fluid table)"}
+    for st in ("f32", "f64"):
+        w = synth.WORKLOADS[f"case2_256_{st}"]
+        r1, r2 = synth.colour_fields(w.shape, w.seed)
+        lat = P.Lattice(w.shape, tau=w.tau, storage=w.storage, device=0, model="colour_gradient", sigma=w.sigma,
+                        beta=w.beta)
+        try:
+            lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+            lat.step(warmup)
+            torch.cuda.synchronize()
+            (a0, b0, *_), _ = lat.totals()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lat.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            (a1, b1, *_), nonfinite = lat.totals()
+        finally:
+            lat.close()
+        glups = w.nodes / (ms * 1e-3) / 1e9
+        bpl = 2 * 19 * 2 * BYTES_PER_VALUE[st]
+        out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
+                   "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
+                   "mass_drift": max(abs(a1 - a0) / a0, abs(b1 - b0) / b0), "nonfinite": nonfinite}
+    return out
+
+
 def adjoint_run(P, torch, synth, every: int = 50):
     """Forward (with checkpoint saves) and backward (recompute + adjoint) of
     J = sum (rho_A(T) - target)^2 on the 128^3 float32 gradient workload."""
@@ -392,6 +427,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-single", action="store_true", help="skip the single-fluid (case 1) timing")
+    ap.add_argument("--no-cg", action="store_true", help="skip the colour-gradient (case 2) timing")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reduced-precision error report")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass", "fused_staged"])
     ap.add_argument("--calibrate", action="store_true",
@@ -487,6 +523,12 @@ def main(argv=None) -> int:
         single = single_fluid_run(P, torch, synth)
         log(f"bench: single fluid {single}")
 
+    cg = None
+    if not args.no_cg:
+        log("bench: colour gradient (case 2) 256^3, float32 and float64")
+        cg = colour_gradient_run(P, torch, synth)
+        log(f"bench: colour gradient {cg}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -517,6 +559,7 @@ def main(argv=None) -> int:
         "adjoint_forward_ratio": None if adjoint is None else adjoint["ratio"],
         "adjoint": adjoint,
         "single_fluid": single,
+        "colour_gradient": cg,
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),
