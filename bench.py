@@ -183,7 +183,28 @@ def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000), restart=(1
     return out
 
 
-def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10):
+def oracle_sample(name, w, planes, steps, make_state, advance):
+    """Time an FP64 oracle on the first ``planes`` z-planes of a workload's
+    initial state (bounded CPU time); returns a cpu_baseline object."""
+    nz, ny, nx = w.shape
+    planes = min(nz, planes)
+    f = make_state((planes, ny, nx))
+    t0 = time.perf_counter()
+    advance(f, steps)
+    dt = time.perf_counter() - t0
+    nodes = planes * ny * nx
+    return {
+        "value": nodes * steps / dt / 1e9,
+        "unit": "GLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} steps of the float64 NumPy {name} oracle on a {nx}x{ny}x{planes} slab of the {w.name} "
+                  f"initial state ({nodes} of {w.nodes} nodes, {dt:.1f} s; NumPy elementwise work is "
+                  f"single-threaded)",
+    }
+
+
+def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu: bool = False):
     """The single-fluid fused step (the paper's case 1) on 256^3 in float32
     and float64: GLUPS and the fraction of the HBM roofline at 19 values read
     and 19 written per node."""
@@ -213,10 +234,18 @@ def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10):
         out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
                    "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4), "mass_drift": abs(m1 - m0) / m0,
                    "nonfinite": nonfinite}
+    if cpu:
+        from oracle import lb_single as S
+
+        w = synth.WORKLOADS["case1_256_f64"]
+        rho, _ = synth.fluid_fields(w.shape, w.amp, w.seed)
+        out["cpu_baseline"] = oracle_sample("single-fluid", w, 64, 4,
+                                            lambda sh: S.init_equilibrium(rho[:sh[0]]),
+                                            lambda f, n: S.step(f, w.tau[0], n=n))
     return out
 
 
-def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10):
+def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu: bool = False):
     """The colour-gradient step (the paper's case 2, two immiscible fluids) on
     256^3 in float32 and float64: GLUPS and the fraction of the HBM roofline
     at 38 values read and 38 written per node."""
@@ -248,6 +277,15 @@ def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10):
         out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
                    "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
                    "mass_drift": max(abs(a1 - a0) / a0, abs(b1 - b0) / b0), "nonfinite": nonfinite}
+    if cpu:
+        from oracle import lb_cg as CG
+
+        w = synth.WORKLOADS["case2_256_f64"]
+        r1, r2 = synth.colour_fields(w.shape, w.seed)
+        p = CG.Params(w.tau, w.sigma, w.beta)
+        out["cpu_baseline"] = oracle_sample("colour-gradient", w, 32, 3,
+                                            lambda sh: CG.init_equilibrium(r1[:sh[0]], r2[:sh[0]]),
+                                            lambda f, n: CG.step(f, p, n=n))
     return out
 
 
@@ -520,13 +558,13 @@ def main(argv=None) -> int:
     single = None
     if not args.no_single:
         log("bench: single fluid (case 1) 256^3, float32 and float64")
-        single = single_fluid_run(P, torch, synth)
+        single = single_fluid_run(P, torch, synth, cpu=not args.no_cpu_baseline)
         log(f"bench: single fluid {single}")
 
     cg = None
     if not args.no_cg:
         log("bench: colour gradient (case 2) 256^3, float32 and float64")
-        cg = colour_gradient_run(P, torch, synth)
+        cg = colour_gradient_run(P, torch, synth, cpu=not args.no_cpu_baseline)
         log(f"bench: colour gradient {cg}")
 
     cpu = None
