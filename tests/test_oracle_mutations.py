@@ -72,6 +72,26 @@ COLOUR = [
     ("cg: A without omega", "A = (2.25 * p.sigma) * omega", "A = 2.25 * p.sigma"),
 ]
 
+PARTICLES = [
+    ("particles: surface velocity r_b x omega as printed",
+     "    ub = [v[..., 0] + (w[..., 1] * rb[2] - w[..., 2] * rb[1]),\n"
+     "          v[..., 1] + (w[..., 2] * rb[0] - w[..., 0] * rb[2]),\n"
+     "          v[..., 2] + (w[..., 0] * rb[1] - w[..., 1] * rb[0])]",
+     "    ub = [v[..., 0] + (rb[1] * w[..., 2] - rb[2] * w[..., 1]),\n"
+     "          v[..., 1] + (rb[2] * w[..., 0] - rb[0] * w[..., 2]),\n"
+     "          v[..., 2] + (rb[0] * w[..., 1] - rb[1] * w[..., 0])]"),
+    ("particles: moving-wall term halved", "return (6.0 * W[i]) * (rho * cub), rb", "return (3.0 * W[i]) * (rho * cub), rb"),
+    ("particles: moving-wall term at unit density", "return (6.0 * W[i]) * (rho * cub), rb",
+     "return (6.0 * W[i]) * cub, rb"),
+    ("particles: link force counts the reflected population once", "t = (g + g) + Wi", "t = g + Wi"),
+    ("particles: covered momentum not handed over", "                sign = 1.0", "                sign = 0.0"),
+    ("particles: uncovered node starts at rest",
+     "vals = O.equilibrium(np.float64(rho0), np.float64(ub[0]), np.float64(ub[1]), np.float64(ub[2]))",
+     "vals = O.equilibrium(np.float64(rho0), np.float64(0.0), np.float64(0.0), np.float64(0.0))"),
+    ("particles: torque sign", "Ti = [rb[1] * Fi[2] - rb[2] * Fi[1], rb[2] * Fi[0] - rb[0] * Fi[2], rb[0] * Fi[1] - rb[1] * Fi[0]]",
+     "Ti = [rb[2] * Fi[1] - rb[1] * Fi[2], rb[0] * Fi[2] - rb[2] * Fi[0], rb[1] * Fi[0] - rb[0] * Fi[1]]"),
+]
+
 RUNNER = r"""
 import importlib.util, sys
 sys.path.insert(0, {root!r})
@@ -124,6 +144,13 @@ def test_single_fluid_pins_catch_planted_mistake(name, old, new):
 def test_colour_gradient_pins_catch_planted_mistake(name, old, new):
     tests = [os.path.join(TESTS, "test_oracle_cg.py")]
     rc = _run_mutant("lb_cg.py", "oracle.lb_cg", "lb_cg", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
+@pytest.mark.parametrize("name,old,new", PARTICLES, ids=[m[0] for m in PARTICLES])
+def test_particle_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_particles.py")]
+    rc = _run_mutant("lb_particles.py", "oracle.lb_particles", "lb_particles", old, new, tests)
     assert rc != 0, f"no pin failed for planted mistake: {name}"
 
 
