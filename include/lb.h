@@ -280,6 +280,46 @@ lb_status lb1_moments(lb1_ctx* ctx, double* rho, double* u, int on_device);
 lb_status lb1_get_populations(lb1_ctx* ctx, double* f, int on_device);
 lb_status lb1_totals(lb1_ctx* ctx, double out[4], int* nonfinite);
 
+/* ---- Moving particles in the single-fluid step (the paper's particle
+ * solver: Sec. 2, Eq. PARDYN; Sec. 3; Appendix, Eqs. UPI, LADDFLBE,
+ * FORCEPP, FORCEPARTEQ, TORQUEPARTEQ) ---------------------------------------
+ * lb1_set_particles places `count` rigid spheres of one radius and mass in
+ * the current fluid state (call it after lb1_set_fields, which drops any
+ * particles).  Host arrays [count][3], float64:
+ *   pos   centres, each coordinate in [0, L) (x, y, z);
+ *   vel   velocities (NULL = 0), each component below 0.5 in magnitude;
+ *   omega angular velocities (NULL = 0).
+ * A node belongs to a particle when its distance d from the centre meets
+ * (d_x d_x + d_y d_y) + d_z d_z <= radius^2.  A node inside two particles
+ * belongs to the lower index.  The populations of particle nodes are
+ * discarded.  mass may be +inf (the particle then keeps its velocities);
+ * the moment of inertia is (2/5) mass radius^2.  Particles already placed
+ * are removed first: their nodes turn to fluid at rest, f_i = w_i rho0[0]
+ * (count = 0 only removes).
+ * lb1_step then advances fluid and particles together.
+ *   - Links from a fluid node into a particle bounce back with
+ *     f_ibar = f*_i - 2 rho w_i (u_b . c_i) / c_s^2, where rho is the fluid
+ *     node's density and u_b = v + omega x r_b at the link midpoint r_b.
+ *   - The particle receives c_i (f*_i + f_ibar) per link, and r_b x that as
+ *     torque.  These are summed in float64 in a fixed order.
+ *   - Leap-frog: v += F / m, omega += T / I, then the centre moves by v.
+ *   - Nodes covered by the move give their momentum to the particle.  Nodes
+ *     uncovered start at f^eq(rho0[0], u_b) and take that momentum from it.
+ *   - Total momentum, fluid plus particles, is conserved to rounding.
+ * lb1_get_particles copies the particle state to host arrays [count][3]
+ * (any may be NULL): positions, velocities, angular velocities, and the
+ * force and torque of the last step.
+ * Storage LB_F64 or LB_F32.  Not with fixed solids from lb1_set_fields.
+ * Each particle's box, floor(2 radius) + 4 nodes, must fit the lattice on
+ * every axis.
+ * Errors: LB_EINVAL (NULL ctx or pos, bad radius, mass, position or speed;
+ * fixed solids; LB_F16_SHIFTED; box larger than the lattice), LB_ESTATE
+ * (lb1_set_particles before lb1_set_fields; lb1_get_particles without
+ * particles), LB_ENOMEM, LB_EDEVICE. */
+lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double mass, const double* pos,
+                            const double* vel, const double* omega);
+lb_status lb1_get_particles(lb1_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque);
+
 /* Human-readable text for a status code. */
 const char* lb_strerror(lb_status status);
 

@@ -13,6 +13,7 @@
 #include "lb_adjoint.h"
 #include "lb_fused.h"
 #include "lb_kernels.h"
+#include "lb_particles.h"
 #include "lb_single.h"
 
 using namespace lbd;
@@ -574,6 +575,14 @@ struct lb1_ctx {
   double* plane = nullptr;
   bool has_state = false;
   hipStream_t stream = nullptr;
+  // moving particles (lb1_set_particles)
+  int np = 0;
+  int part_cap = 0;         // particles the buffer below holds
+  PartState ps{};
+  double* part = nullptr;   // [5][P][3]: pos, vel, omg, force, torque
+  int* owner[2] = {nullptr, nullptr};
+  int ocur = 0;
+  double* rho_buf = nullptr;  // [N]
 };
 
 namespace {
@@ -597,9 +606,13 @@ lb_status alloc1(void** ptr, size_t bytes) {
   return LB_OK;
 }
 
+// mask of solid nodes (fixed solids or particles), or nullptr
+const uint8_t* solid_of(const lb1_ctx* ctx) { return (ctx->has_solid || ctx->np > 0) ? ctx->mask : nullptr; }
+
 void free1(lb1_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
-  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->mask, ctx->partial, ctx->result, ctx->flag, ctx->plane};
+  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->mask,     ctx->partial,  ctx->result, ctx->flag,
+                  ctx->plane,   ctx->part,    ctx->owner[0], ctx->owner[1], ctx->rho_buf};
   for (void* b : bufs)
     if (b != nullptr) (void)hipFree(b);
 }
@@ -1325,6 +1338,7 @@ lb_status lb1_set_fields(lb1_ctx* ctx, const double* rho, const double* u, const
     }
   }
   ctx->has_solid = solid != nullptr;
+  ctx->np = 0;  // new fields drop the particles
   // solid nodes are never written by a step, so both grids start from zero
   for (int b = 0; b < 2; ++b)
     if (hipMemsetAsync(ctx->grid[b], 0, ctx->grid_bytes, ctx->stream) != hipSuccess) return finish(LB_EDEVICE);
@@ -1347,6 +1361,33 @@ lb_status lb1_step(lb1_ctx* ctx, int32_t n) {
   if (n == 0) return LB_OK;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  if (ctx->np > 0) {
+    // fluid step, forces and leap-frog, owner map of the new positions, covering/uncovering
+    return by_storage_id(ctx->p.storage, [&](auto tag) {
+      constexpr int ST = decltype(tag)::value;
+      using store = typename StorageTraits<ST>::store_t;
+      if constexpr (ST == ST_F16S) {
+        return LB_EINVAL;
+      } else {
+        for (int s = 0; s < n; ++s) {
+          const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+          store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+          const int* own = ctx->owner[ctx->ocur];
+          int* own_new = ctx->owner[ctx->ocur ^ 1];
+          k1p_step<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, own, ctx->ps, ctx->rho_buf,
+                                                                         ctx->g, ctx->c);
+          kp_force_move<ST><<<ctx->np, 64, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g, ctx->c);
+          kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(own_new, ctx->g.N);
+          kp_owner_scatter<<<ctx->np, kBlock, 0, ctx->stream>>>(own_new, ctx->ps, ctx->g);
+          kp_remap<ST><<<ctx->np, 64, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps, ctx->g, ctx->c);
+          LB_HIP(hipGetLastError());
+          ctx->cur ^= 1;
+          ctx->ocur ^= 1;
+        }
+        return LB_OK;
+      }
+    });
+  }
   const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
   return by_storage_id(ctx->p.storage, [&](auto tag) {
     constexpr int ST = decltype(tag)::value;
@@ -1380,7 +1421,7 @@ lb_status lb1_moments(lb1_ctx* ctx, double* rho, double* u, int on_device) {
     dr = rho ? static_cast<double*>(tmp) : nullptr;
     du = u ? static_cast<double*>(tmp) + N : nullptr;
   }
-  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  const uint8_t* m = solid_of(ctx);
   lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
     constexpr int ST = decltype(tag)::value;
     k1_moments<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
@@ -1409,7 +1450,7 @@ lb_status lb1_get_populations(lb1_ctx* ctx, double* f, int on_device) {
     lb_status st = alloc1(reinterpret_cast<void**>(&ctx->plane), sizeof(double) * N);
     if (st != LB_OK) return st;
   }
-  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  const uint8_t* m = solid_of(ctx);
   for (int plane = 0; plane < Q; ++plane) {
     double* dst = on_device ? f + plane * N : ctx->plane;
     lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
@@ -1435,7 +1476,7 @@ lb_status lb1_totals(lb1_ctx* ctx, double out[4], int* nonfinite) {
   if (!dg.ok) return LB_EDEVICE;
   int blocks = blocks_for(ctx->g.N);
   if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
-  const uint8_t* m = ctx->has_solid ? ctx->mask : nullptr;
+  const uint8_t* m = solid_of(ctx);
   lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
     constexpr int ST = decltype(tag)::value;
     k_totals_partial<ST, 1><<<blocks, kBlock, 0, ctx->stream>>>(
@@ -1454,6 +1495,111 @@ lb_status lb1_totals(lb1_ctx* ctx, double out[4], int* nonfinite) {
   const int nf = r[5] != 0.0 ? 1 : 0;
   if (nonfinite != nullptr) *nonfinite = nf;
   return nf ? LB_ENONFINITE : LB_OK;
+}
+
+lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double mass, const double* pos,
+                            const double* vel, const double* omega) {
+  if (ctx == nullptr || count < 0) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  if (count > 0 && (pos == nullptr || ctx->has_solid || ctx->p.storage == LB_F16_SHIFTED)) return LB_EINVAL;
+  auto release = [&]() -> lb_status {  // the current particles' nodes turn to fluid at rest
+    if (ctx->np == 0) return LB_OK;
+    DeviceGuard dg(ctx->p.device);
+    if (!dg.ok) return LB_EDEVICE;
+    lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+      constexpr int ST = decltype(tag)::value;
+      kp_release<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+          static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->mask, ctx->p.rho0[0], ctx->g,
+          ctx->c);
+      return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+    });
+    if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
+    if (st == LB_OK) ctx->np = 0;
+    return st;
+  };
+  if (count == 0) return release();
+  if (!is_finite(radius) || !(radius > 0.0) || std::isnan(mass) || !(mass > 0.0)) return LB_EINVAL;
+  const int box = static_cast<int>(std::floor(2.0 * radius)) + 4;
+  if (box > ctx->g.nx || box > ctx->g.ny || box > ctx->g.nz) return LB_EINVAL;  // a particle's box must fit the lattice
+  const double L[3] = {double(ctx->g.nx), double(ctx->g.ny), double(ctx->g.nz)};
+  const size_t P = static_cast<size_t>(count);
+  std::vector<double> host(15 * P, 0.0);
+  for (size_t q = 0; q < P; ++q)
+    for (int a = 0; a < 3; ++a) {
+      const double r = pos[3 * q + a];
+      const double v = vel ? vel[3 * q + a] : 0.0;
+      const double w = omega ? omega[3 * q + a] : 0.0;
+      if (!is_finite(r) || r < 0.0 || r >= L[a]) return LB_EINVAL;
+      if (!is_finite(v) || !(std::fabs(v) < 0.5) || !is_finite(w)) return LB_EINVAL;  // under half a node per step
+      host[3 * q + a] = r;
+      host[3 * P + 3 * q + a] = v;
+      host[6 * P + 3 * q + a] = w;
+    }
+  {
+    lb_status st = release();
+    if (st != LB_OK) return st;
+  }
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  if (ctx->part != nullptr && ctx->part_cap < count) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->part);
+    ctx->part = nullptr;
+    ctx->part_cap = 0;
+  }
+  if (ctx->part == nullptr) {
+    if (alloc1(reinterpret_cast<void**>(&ctx->part), sizeof(double) * 15 * P) != LB_OK) return LB_ENOMEM;
+    ctx->part_cap = count;
+  }
+  for (int b = 0; b < 2; ++b)
+    if (ctx->owner[b] == nullptr && alloc1(reinterpret_cast<void**>(&ctx->owner[b]), sizeof(int) * N) != LB_OK)
+      return LB_ENOMEM;
+  if (ctx->rho_buf == nullptr && alloc1(reinterpret_cast<void**>(&ctx->rho_buf), sizeof(double) * N) != LB_OK)
+    return LB_ENOMEM;
+  if (ctx->mask == nullptr && alloc1(reinterpret_cast<void**>(&ctx->mask), N) != LB_OK) return LB_ENOMEM;
+  PartState& ps = ctx->ps;
+  ps.pos = ctx->part;
+  ps.vel = ctx->part + 3 * P;
+  ps.omg = ctx->part + 6 * P;
+  ps.force = ctx->part + 9 * P;
+  ps.torque = ctx->part + 12 * P;
+  ps.count = count;
+  ps.box = box;
+  ps.radius = radius;
+  ps.r2 = radius * radius;
+  ps.mass = mass;
+  ps.inertia = 0.4 * mass * radius * radius;
+  ps.rho0 = ctx->p.rho0[0];
+  LB_HIP(hipMemcpyAsync(ctx->part, host.data(), sizeof(double) * 15 * P, hipMemcpyHostToDevice, ctx->stream));
+  ctx->ocur = 0;
+  kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ctx->owner[0], ctx->g.N);
+  kp_owner_scatter<<<count, kBlock, 0, ctx->stream>>>(ctx->owner[0], ps, ctx->g);
+  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    kp_apply_owner<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->owner[0], ctx->mask, ctx->g);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+  if (st != LB_OK) return st;
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->np = count;
+  return LB_OK;
+}
+
+lb_status lb1_get_particles(lb1_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque) {
+  if (ctx == nullptr) return LB_EINVAL;
+  if (ctx->np == 0) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t P = static_cast<size_t>(ctx->np);
+  double* outs[5] = {pos, vel, omega, force, torque};
+  const double* srcs[5] = {ctx->ps.pos, ctx->ps.vel, ctx->ps.omg, ctx->ps.force, ctx->ps.torque};
+  for (int k = 0; k < 5; ++k)
+    if (outs[k] != nullptr)
+      LB_HIP(hipMemcpyAsync(outs[k], srcs[k], sizeof(double) * 3 * P, hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,327 @@
+// Moving rigid spheres in the single-fluid step: the paper's particle solver
+// (Sec. 2, Eq. PARDYN with leap-frog; Sec. 3 step order; Appendix, Eqs. UPI,
+// LADDFLBE, FORCEPP, FORCEPARTEQ, TORQUEPARTEQ), HIP kernels.
+//
+// One step, t -> t + 1 (each line one launch):
+//   k1p_step         collide fluid nodes, push; links into a particle bounce
+//                    back with the moving-wall correction
+//                    W_i = 2 rho w_i (u_b . c_i) / c_s^2, u_b = v + omega x r_b;
+//                    solid nodes get zero populations; fluid nodes with such
+//                    a link record their density for the force pass
+//   kp_force_move    one wave per particle: force and torque summed over its
+//                    links in float64 in a fixed order, then the leap-frog
+//                    update of velocity, angular velocity and position
+//   kp_owner_fill,
+//   kp_owner_scatter owner map of the new positions (lowest index wins)
+//   kp_remap         one wave per particle: nodes covered by the move hand
+//                    their momentum to the particle and are emptied; nodes
+//                    uncovered start at f^eq(rho0, u_b) and take theirs from
+//                    the particle
+// Particle arithmetic (positions, surface velocities, W_i, forces) is
+// float64 whatever the storage: the paper accumulates particle forces in
+// double precision because the link terms cancel strongly.
+//
+// Fixed summation order of a particle's link and covering sums, so that
+// they are reproducible bit for bit.  The particle's box has S nodes per axis
+// from lo_a = floor(r_a - R) - 1, numbered b = j_x + S (j_y + S j_z).  Lane l
+// of the particle's wave takes b = l, l + 64, ... in order, and at each node
+// directions i = 1..18 in order.  The 64 lane sums are then combined by a
+// butterfly, a_l <- a_l + a_(l xor s) for s = 32, 16, ..., 1.
+#pragma once
+
+#include "lb_fused.h"
+#include "lb_kernels.h"
+
+namespace lbd {
+
+constexpr int kOwnerFluid = 0x7fffffff;
+
+struct PartState {
+  double* pos;     // [P][3], in [0, L)
+  double* vel;     // [P][3], at half steps
+  double* omg;     // [P][3], at half steps
+  double* force;   // [P][3], of the last step
+  double* torque;  // [P][3]
+  int count;
+  int box;         // S = floor(2R) + 4
+  double radius, r2, mass, inertia, rho0;
+};
+
+__device__ __forceinline__ int wrap_coord(int c, int L) {
+  c %= L;
+  return c < 0 ? c + L : c;
+}
+
+// Nearest periodic image of a coordinate difference.
+__device__ __forceinline__ double fold(double d, double L) {
+  if (d > 0.5 * L) d = d - L;
+  if (d < -0.5 * L) d = d + L;
+  return d;
+}
+
+// W_i and the link midpoint r_b (relative to the particle) for the link
+// from fluid node (x, y, z) in direction i into particle p.
+__device__ __forceinline__ double wall_term(int i, int x, int y, int z, double rho, int p, const PartState& ps,
+                                            const Geometry& g, double (&rb)[3]) {
+  const double* r = ps.pos + 3 * p;
+  const double* v = ps.vel + 3 * p;
+  const double* w = ps.omg + 3 * p;
+  rb[0] = fold((double(x) + 0.5 * CX[i]) - r[0], double(g.nx));
+  rb[1] = fold((double(y) + 0.5 * CY[i]) - r[1], double(g.ny));
+  rb[2] = fold((double(z) + 0.5 * CZ[i]) - r[2], double(g.nz));
+  const double ubx = v[0] + (w[1] * rb[2] - w[2] * rb[1]);
+  const double uby = v[1] + (w[2] * rb[0] - w[0] * rb[2]);
+  const double ubz = v[2] + (w[0] * rb[1] - w[1] * rb[0]);
+  const double cub = cdot<double>(i, ubx, uby, ubz);
+  return (6.0 * weight<double>(i)) * (rho * cub);
+}
+
+// Single-fluid step with particles.  One work-item per node, as k1_step.
+template <int ST>
+__global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
+                                                   const int* __restrict__ owner, PartState ps,
+                                                   double* __restrict__ rho_buf, Geometry g, StepCoeffs c) {
+  using real = real_t<ST>;
+  const int b = fused_work_item(blockIdx.x, gridDim.x, gridDim.x);
+  const int n = b * kBlock + threadIdx.x;
+  if (n >= g.N) return;
+  if (owner[n] != kOwnerFluid) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fout[(long long)i * g.Npad + n] = store_t<ST>(0);
+    return;
+  }
+  int x, y, z;
+  node_xyz(n, g, x, y, z);
+  int nb[Q];
+  neighbours(x, y, z, g, nb);
+  real f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = decode<ST>(fin[(long long)i * g.Npad + n], c.shift[0][i]);
+  const real rho = density<real>(f);
+  const real ux = lattice_sum<0, 0, real>(f) / rho;
+  const real uy = lattice_sum<1, 0, real>(f) / rho;
+  const real uz = lattice_sum<2, 0, real>(f) / rho;
+  real fs[Q];
+  if constexpr (sizeof(real) == 8) {
+    const real om = coef_om<real>(c, 0), omc = coef_omc<real>(c, 0);
+    const real t15 = real(1.5) * ((ux * ux + uy * uy) + uz * uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const real cu = cdot<real>(i, ux, uy, uz);
+      const real feq = (weight<real>(i) * rho) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+      fs[i] = omc * f[i] + om * feq;
+    }
+  } else {
+    relax_f32(f, fs, rho, ux, uy, uz, coef_om<real>(c, 0), coef_omc<real>(c, 0));
+  }
+  bool linked = false;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    long long dst = (long long)i * g.Npad + nb[i];
+    real val = fs[i];
+    if (i != 0) {
+      const int p = owner[nb[i]];
+      if (p != kOwnerFluid) {
+        double rb[3];
+        const double W = wall_term(i, x, y, z, static_cast<double>(rho), p, ps, g, rb);
+        dst = (long long)OPP[i] * g.Npad + n;
+        val = fs[i] - static_cast<real>(W);
+        linked = true;
+      }
+    }
+    fout[dst] = encode<ST>(val, c.shift[0][i]);  // w_opp(i) = w_i: same float16 offset
+  }
+  if (linked) rho_buf[n] = static_cast<double>(rho);
+}
+
+__device__ __forceinline__ double wave_sum_xor(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v = v + __shfl_xor(v, s, 64);
+  return v;
+}
+
+// Box node b of a particle at r: unwrapped coordinates and the wrapped node index.
+__device__ __forceinline__ int box_node(int b, const int (&lo)[3], int S, const Geometry& g, int (&cc)[3]) {
+  cc[0] = lo[0] + b % S;
+  cc[1] = lo[1] + (b / S) % S;
+  cc[2] = lo[2] + b / (S * S);
+  return wrap_coord(cc[0], g.nx) + g.nx * (wrap_coord(cc[1], g.ny) + g.ny * wrap_coord(cc[2], g.nz));
+}
+
+__device__ __forceinline__ void box_origin(const double* r, double R, int (&lo)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lo[a] = static_cast<int>(floor(r[a] - R)) - 1;
+}
+
+// Force and torque from the links of the step just made (fnew = f(t+1),
+// owner of step t), then leap-frog: v += F/m, omega += T/I, r += v.
+// One 64-lane workgroup per particle.
+template <int ST>
+__global__ void __launch_bounds__(64) kp_force_move(const store_t<ST>* __restrict__ fnew, const int* __restrict__ owner,
+                                                    const double* __restrict__ rho_buf, PartState ps, Geometry g,
+                                                    StepCoeffs c) {
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  int lo[3];
+  box_origin(ps.pos + 3 * p, ps.radius, lo);
+  const int S = ps.box, nbox = S * S * S;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = lane; b < nbox; b += 64) {
+    int cc[3];
+    const int n = box_node(b, lo, S, g, cc);
+    if (owner[n] != p) continue;
+    const int xs = n % g.nx, ys = (n / g.nx) % g.ny, zs = n / (g.nx * g.ny);
+    for (int i = 1; i < Q; ++i) {
+      const int xf = wrap_coord(xs - CX[i], g.nx), yf = wrap_coord(ys - CY[i], g.ny), zf = wrap_coord(zs - CZ[i], g.nz);
+      const int nf = xf + g.nx * (yf + g.ny * zf);
+      if (owner[nf] != kOwnerFluid) continue;
+      double rb[3];
+      const double W = wall_term(i, xf, yf, zf, rho_buf[nf], p, ps, g, rb);
+      const double gv = static_cast<double>(decode<ST>(fnew[(long long)OPP[i] * g.Npad + nf], c.shift[0][OPP[i]]));
+      const double t = (gv + gv) + W;
+      const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
+                           CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
+      acc[0] = acc[0] + F[0];
+      acc[1] = acc[1] + F[1];
+      acc[2] = acc[2] + F[2];
+      acc[3] = acc[3] + (rb[1] * F[2] - rb[2] * F[1]);
+      acc[4] = acc[4] + (rb[2] * F[0] - rb[0] * F[2]);
+      acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc[d] = wave_sum_xor(acc[d]);
+  if (lane == 0) {
+    const double L[3] = {double(g.nx), double(g.ny), double(g.nz)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ps.force[3 * p + a] = acc[a];
+      ps.torque[3 * p + a] = acc[3 + a];
+      const double v = ps.vel[3 * p + a] + acc[a] / ps.mass;
+      ps.vel[3 * p + a] = v;
+      ps.omg[3 * p + a] = ps.omg[3 * p + a] + acc[3 + a] / ps.inertia;
+      double r = ps.pos[3 * p + a] + v;
+      if (r >= L[a]) r = r - L[a];
+      if (r < 0.0) r = r + L[a];
+      ps.pos[3 * p + a] = r;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) kp_owner_fill(int* __restrict__ owner, int N) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n < N) owner[n] = kOwnerFluid;
+}
+
+// owner[x] = min over particles containing x.  One workgroup per particle.
+__global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ owner, PartState ps, Geometry g) {
+  const int p = blockIdx.x;
+  const double* r = ps.pos + 3 * p;
+  int lo[3];
+  box_origin(r, ps.radius, lo);
+  const int S = ps.box, nbox = S * S * S;
+  for (int b = threadIdx.x; b < nbox; b += kBlock) {
+    int cc[3];
+    const int n = box_node(b, lo, S, g, cc);
+    const double dx = double(cc[0]) - r[0], dy = double(cc[1]) - r[1], dz = double(cc[2]) - r[2];
+    if ((dx * dx + dy * dy) + dz * dz <= ps.r2) atomicMin(owner + n, p);
+  }
+}
+
+// Covering and uncovering after the move; mask follows the new owner map.
+template <int ST>
+__global__ void __launch_bounds__(64) kp_remap(store_t<ST>* __restrict__ f, const int* __restrict__ owner_old,
+                                               const int* __restrict__ owner_new, uint8_t* __restrict__ mask,
+                                               PartState ps, Geometry g, StepCoeffs c) {
+  using real = real_t<ST>;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* r = ps.pos + 3 * p;
+  int lo[3];
+  box_origin(r, ps.radius, lo);
+  const int S = ps.box, nbox = S * S * S;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = lane; b < nbox; b += 64) {
+    int cc[3];
+    const int n = box_node(b, lo, S, g, cc);
+    const bool covered = owner_new[n] == p && owner_old[n] == kOwnerFluid;
+    const bool uncovered = owner_old[n] == p && owner_new[n] == kOwnerFluid;
+    if (!covered && !uncovered) continue;
+    const double d[3] = {double(cc[0]) - r[0], double(cc[1]) - r[1], double(cc[2]) - r[2]};
+    real vals[Q];
+    double sign;
+    if (covered) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        vals[i] = decode<ST>(f[(long long)i * g.Npad + n], c.shift[0][i]);
+        f[(long long)i * g.Npad + n] = store_t<ST>(0);
+      }
+      mask[n] = 1;
+      sign = 1.0;
+    } else {
+      const double* v = ps.vel + 3 * p;
+      const double* w = ps.omg + 3 * p;
+      const double ub[3] = {v[0] + (w[1] * d[2] - w[2] * d[1]), v[1] + (w[2] * d[0] - w[0] * d[2]),
+                            v[2] + (w[0] * d[1] - w[1] * d[0])};
+      const real ux = static_cast<real>(ub[0]), uy = static_cast<real>(ub[1]), uz = static_cast<real>(ub[2]);
+      const real rho0 = static_cast<real>(ps.rho0);
+      const real t15 = real(1.5) * ((ux * ux + uy * uy) + uz * uz);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real cu = cdot<real>(i, ux, uy, uz);
+        const real feq = (weight<real>(i) * rho0) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+        const store_t<ST> s = encode<ST>(feq, c.shift[0][i]);
+        f[(long long)i * g.Npad + n] = s;
+        vals[i] = decode<ST>(s, c.shift[0][i]);  // the stored value, so that the exchange is exact
+      }
+      mask[n] = 0;
+      sign = -1.0;
+    }
+    const double m[3] = {sign * static_cast<double>(lattice_sum<0, 0, real>(vals)),
+                         sign * static_cast<double>(lattice_sum<1, 0, real>(vals)),
+                         sign * static_cast<double>(lattice_sum<2, 0, real>(vals))};
+    acc[0] = acc[0] + m[0];
+    acc[1] = acc[1] + m[1];
+    acc[2] = acc[2] + m[2];
+    acc[3] = acc[3] + (d[1] * m[2] - d[2] * m[1]);
+    acc[4] = acc[4] + (d[2] * m[0] - d[0] * m[2]);
+    acc[5] = acc[5] + (d[0] * m[1] - d[1] * m[0]);
+  }
+#pragma unroll
+  for (int dd = 0; dd < 6; ++dd) acc[dd] = wave_sum_xor(acc[dd]);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ps.vel[3 * p + a] = ps.vel[3 * p + a] + acc[a] / ps.mass;
+      ps.omg[3 * p + a] = ps.omg[3 * p + a] + acc[3 + a] / ps.inertia;
+    }
+  }
+}
+
+// Initial owner-based state: zero the populations of solid nodes, mask = owner != fluid.
+template <int ST>
+__global__ void __launch_bounds__(kBlock) kp_apply_owner(store_t<ST>* __restrict__ f, const int* __restrict__ owner,
+                                                         uint8_t* __restrict__ mask, Geometry g) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= g.N) return;
+  const bool solid = owner[n] != kOwnerFluid;
+  mask[n] = solid ? 1 : 0;
+  if (solid)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[(long long)i * g.Npad + n] = store_t<ST>(0);
+}
+
+// Particles removed: their nodes turn to fluid at rest, f_i = w_i rho0.
+template <int ST>
+__global__ void __launch_bounds__(kBlock) kp_release(store_t<ST>* __restrict__ f, uint8_t* __restrict__ mask,
+                                                     double rho0, Geometry g, StepCoeffs c) {
+  using real = real_t<ST>;
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= g.N || !mask[n]) return;
+  mask[n] = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    f[(long long)i * g.Npad + n] = encode<ST>(weight<real>(i) * static_cast<real>(rho0), c.shift[0][i]);
+}
+
+}  // namespace lbd

@@ -93,6 +93,8 @@ _SIGNATURES = [
     ("lb1_moments", ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     ("lb1_get_populations", ctypes.c_int, [_P, _P, ctypes.c_int]),
     ("lb1_totals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+    ("lb1_set_particles", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    ("lb1_get_particles", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
 ]
@@ -412,6 +414,40 @@ def lb1_totals(ctx) -> Tuple[Tuple[float, ...], bool]:
     return tuple(out), bool(nf.value)
 
 
+def _host3(a, count: int, what: str):
+    """Host float64 [count][3] array (copied to C order) or None."""
+    import numpy as np
+
+    if a is None:
+        return None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if arr.size != 3 * count:
+        raise ValueError(f"{what}: expected {count} x 3 values, got {arr.size}")
+    return arr
+
+
+def lb1_set_particles(ctx, pos, radius: float, mass: float, vel=None, omega=None) -> None:
+    """Place rigid spheres (host arrays [P][3]); pos=None or empty removes them."""
+    import numpy as np
+
+    if pos is None or np.size(pos) == 0:
+        _check(library().lb1_set_particles(ctx, 0, float(radius), float(mass), None, None, None), "lb1_set_particles")
+        return
+    count = np.size(pos) // 3
+    arrs = [_host3(a, count, w) for a, w in ((pos, "pos"), (vel, "vel"), (omega, "omega"))]
+    ptrs = [None if a is None else ctypes.c_void_p(a.ctypes.data) for a in arrs]
+    _check(library().lb1_set_particles(ctx, count, float(radius), float(mass), *ptrs), "lb1_set_particles")
+
+
+def lb1_get_particles(ctx, count: int):
+    """(pos, vel, omega, force, torque), each a host float64 array [count][3]."""
+    import numpy as np
+
+    outs = [np.empty((count, 3)) for _ in range(5)]
+    _check(library().lb1_get_particles(ctx, *[ctypes.c_void_p(o.ctypes.data) for o in outs]), "lb1_get_particles")
+    return tuple(outs)
+
+
 class SingleFluid:
     """A single-fluid lattice (the paper's case 1) on one GPU: owns an
     lb1_ctx.  ``shape`` is (nz, ny, nx); arrays as for ``Lattice``."""
@@ -427,6 +463,7 @@ class SingleFluid:
         p.stream = stream if stream is not None else _current_stream(device)
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
+        self.nparticles = 0
         self.ctx = lb1_create(p)
 
     def close(self):
@@ -448,6 +485,7 @@ class SingleFluid:
 
     def set_fields(self, rho, u=None, solid=None):
         lb1_set_fields(self.ctx, self.n, rho, u, solid)
+        self.nparticles = 0  # new fields drop the particles
 
     def step(self, nsteps: int = 1):
         lb1_step(self.ctx, nsteps)
@@ -460,6 +498,16 @@ class SingleFluid:
 
     def totals(self):
         return lb1_totals(self.ctx)
+
+    def set_particles(self, pos, radius: float, mass: float, vel=None, omega=None):
+        import numpy as np
+
+        lb1_set_particles(self.ctx, pos, radius, mass, vel, omega)
+        self.nparticles = 0 if pos is None else int(np.size(pos) // 3)
+
+    def particles(self):
+        """(pos, vel, omega, force, torque) of the particles, host [P][3] each."""
+        return lb1_get_particles(self.ctx, self.nparticles)
 
 
 class Lattice:

@@ -24,6 +24,7 @@ __all__ = [
     "WORKLOADS",
     "fluid_fields",
     "colour_fields",
+    "particle_mass",
     "sphere_centres",
     "solid_mask",
     "smooth_target",
@@ -75,6 +76,16 @@ WORKLOADS = {
     # two immiscible fluids, colour-gradient model (the paper's case 2: every node pure red or pure
     # blue at random, at rest, periodic cube); tau of both pure fluids, surface tension sigma and
     # recolouring beta are not given by the paper; G, rho0 and amp are unused
+    # moving rigid spheres of radius 5.5 in the single fluid (the paper's case 3 fractions 0.1%, 1% and
+    # 10% of a 256^3 box: 24, 241 and 2407 spheres); at rest, fluid 1 +- U(0.02)
+    "case3a_256_f32": Workload("case3a_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 500, 11,
+                               spheres=24, radius=5.5, sphere_seed=12),
+    "case3b_256_f32": Workload("case3b_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 500, 11,
+                               spheres=241, radius=5.5, sphere_seed=13),
+    "case3c_256_f32": Workload("case3c_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 500, 11,
+                               spheres=2407, radius=5.5, sphere_seed=14),
+    "case3c_256_f64": Workload("case3c_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 500, 11,
+                               spheres=2407, radius=5.5, sphere_seed=14),
     "case2_32_f64": Workload("case2_32_f64", (32, 32, 32), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 200, 9,
                              sigma=0.01, beta=0.7),
     "case2_256_f32": Workload("case2_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 1000, 10,
@@ -108,6 +119,15 @@ def colour_fields(shape, seed: int):
     red = rng.random(tuple(int(s) for s in shape)) < 0.5
     r = np.where(red, 1.0, 0.0)
     return np.ascontiguousarray(r, dtype=np.float64), np.ascontiguousarray(1.0 - r, dtype=np.float64)
+
+
+# Particle mass of the moving-sphere workloads: a sphere 2.2 times as dense as
+# the fluid (silica in water, as the paper's particles), fluid density 1.
+PARTICLE_DENSITY_RATIO = 2.2
+
+
+def particle_mass(radius: float) -> float:
+    return PARTICLE_DENSITY_RATIO * (4.0 / 3.0) * np.pi * radius ** 3
 
 
 def _min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:

@@ -68,7 +68,7 @@ def test_resting_particle_is_the_fixed_solid_single_fluid_step():
 def test_total_momentum_is_conserved_while_particles_move_and_cover_nodes():
     shape = (20, 18, 22)
     rho, u = _fluid(shape, 4)
-    part = PT.Particles(3.2, 60.0, [[6.3, 5.2, 7.1], [15.4, 12.6, 13.2]],
+    part = PT.Particles(3.2, 400.0, [[6.3, 5.2, 7.1], [15.4, 12.6, 13.2]],
                         [[0.08, -0.05, 0.06], [-0.07, 0.06, -0.05]], [[0.0, 0.0, 0.02], [0.02, -0.01, 0.0]])
     f, owner = PT.init(rho, part, u)
     P0 = PT.total_momentum(f, part)
