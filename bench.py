@@ -245,6 +245,72 @@ def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu: b
     return out
 
 
+def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool = False):
+    """Moving rigid spheres (radius 5.5, 2.2 times the fluid density) in the
+    single-fluid step on 256^3: the paper's case-3 volume fractions 0.1%, 1%
+    and 10%, float32 (and float64 at 10%).  GLUPS count every node; the
+    overhead is the time per step over that of the same lattice without
+    particles."""
+    import numpy as np
+
+    out = {"lattice": [256, 256, 256], "radius": 5.5,
+           "paper_context": "34.6 / 37.6 / 56 ms per step (0.484 / 0.446 / 0.299 GLUPS) at 0.1 / 1 / 10% on one V100, "
+                            "single precision, colour-gradient fluid with particles (Sec. 5, particle table)"}
+    base = {}
+    for name in ("case3a_256_f32", "case3b_256_f32", "case3c_256_f32", "case3c_256_f64"):
+        w = synth.WORKLOADS[name]
+        rho, _ = synth.fluid_fields(w.shape, w.amp, w.seed)
+        centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+        lat = P.SingleFluid(w.shape, tau=w.tau[0], storage=w.storage, device=0)
+        try:
+            lat.set_fields(rho.reshape(-1))
+            if w.storage not in base:
+                lat.step(warmup)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                lat.step(steps)
+                e1.record()
+                torch.cuda.synchronize()
+                base[w.storage] = e0.elapsed_time(e1) / steps
+                lat.set_fields(rho.reshape(-1))
+            lat.set_particles(centres, w.radius, synth.particle_mass(w.radius))
+            lat.step(warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lat.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            _, nonfinite = lat.totals()
+        finally:
+            lat.close()
+        phi = w.spheres * (4.0 / 3.0) * np.pi * w.radius ** 3 / w.nodes
+        out[name] = {"spheres": w.spheres, "volume_fraction": round(phi, 5), "glups": round(w.nodes / (ms * 1e-3) / 1e9, 4),
+                     "ms_per_step": round(ms, 4), "no_particles_ms_per_step": round(base[w.storage], 4),
+                     "overhead": round(ms / base[w.storage] - 1.0, 4), "nonfinite": nonfinite}
+    if cpu:
+        from oracle import lb_particles as PT
+
+        sh = (64, 64, 64)
+        count = 38  # 10% of a 64^3 box in spheres of radius 5.5
+        w = synth.WORKLOADS["case3c_256_f64"]
+        centres = synth.sphere_centres(sh, count, w.radius, w.sphere_seed)
+        rho, _ = synth.fluid_fields(sh, w.amp, w.seed)
+        part = PT.Particles(w.radius, synth.particle_mass(w.radius), centres, None, None)
+        f, owner = PT.init(rho, part)
+        t0 = time.perf_counter()
+        PT.step(f, w.tau[0], part, owner, n=2)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 64 ** 3 * 2 / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"2 steps of the float64 NumPy particle oracle on a 64^3 box with {count} "
+                                         f"spheres of radius 5.5 (10%), {dt:.1f} s"}
+    return out
+
+
 def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu: bool = False):
     """The colour-gradient step (the paper's case 2, two immiscible fluids) on
     256^3 in float32 and float64: GLUPS and the fraction of the HBM roofline
@@ -466,6 +532,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-single", action="store_true", help="skip the single-fluid (case 1) timing")
     ap.add_argument("--no-cg", action="store_true", help="skip the colour-gradient (case 2) timing")
+    ap.add_argument("--no-particles", action="store_true", help="skip the moving-particle (case 3 fractions) timing")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reduced-precision error report")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "two_pass", "fused_staged"])
     ap.add_argument("--calibrate", action="store_true",
@@ -567,6 +634,12 @@ def main(argv=None) -> int:
         cg = colour_gradient_run(P, torch, synth, cpu=not args.no_cpu_baseline)
         log(f"bench: colour gradient {cg}")
 
+    particles = None
+    if not args.no_particles:
+        log("bench: moving particles 256^3, 0.1 / 1 / 10% of the volume")
+        particles = particles_run(P, torch, synth, cpu=not args.no_cpu_baseline)
+        log(f"bench: particles {particles}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -598,6 +671,7 @@ def main(argv=None) -> int:
         "adjoint": adjoint,
         "single_fluid": single,
         "colour_gradient": cg,
+        "particles": particles,
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),

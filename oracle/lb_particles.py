@@ -51,18 +51,19 @@ Readings where the paper is silent, garbled, or defers to LBsoft:
 * Solid nodes hold zero populations.  The collision and the equilibrium are
   those of ``lb_single`` / ``lb_oracle``.
 
-Fixed order of the float64 particle sums (so that a GPU doing one wave per
-particle reproduces them bit for bit):
+Fixed order of the float64 particle sums (so that a GPU running one
+256-lane workgroup per particle reproduces them bit for bit):
 
 * Each particle's box has S = floor(2R) + 4 nodes per axis, from
   lo_a = floor(r_pa - R) - 1.  Box nodes are numbered b = j_x + S (j_y + S j_z).
-* For the link sums, 64 partial sums are formed.  Partial l takes box nodes
-  b = l, l + 64, ... in order; at each node it takes directions i = 1..18 in
+* For the link sums, 256 partial sums are formed.  Partial l takes box nodes
+  b = l, l + 256, ... in order; at each node it takes directions i = 1..18 in
   order, adding F_i and r_b x F_i of every link from a fluid node into that
   node (solid, of this particle).  For the covering sums it adds each node's
   single term.
-* The 64 partials are combined by a butterfly: for s = 32, 16, ..., 1,
-  a_l <- a_l + a_(l xor s).  The result is a_0.
+* The partials are combined in four groups of 64 (l = 64 w .. 64 w + 63), each
+  by a butterfly: for s = 32, 16, ..., 1, a_l <- a_l + a_(l xor s).  The
+  group results A_0..A_3 (at l = 64 w) give (A_0 + A_1) + (A_2 + A_3).
 * Scalar arithmetic orders:
   * W_i = (6 w_i) (rho (c_i . u_b)), with
     u_b = v + (omega_y r_z - omega_z r_y, omega_z r_x - omega_x r_z, omega_x r_y - omega_y r_x).
@@ -209,21 +210,24 @@ def fluid_step(f: np.ndarray, tau: float, part: Particles, owner: np.ndarray):
     return out, rho
 
 
+LANES = 256
+
+
 def _lane_sum(terms: np.ndarray) -> np.ndarray:
     """Sum terms [nodes][k][6] (box order, k terms per node) in the fixed order
     of the module docstring."""
     nb, k, d = terms.shape
-    pad = (-nb) % 64
+    pad = (-nb) % LANES
     t = np.concatenate([terms, np.zeros((pad, k, d))]) if pad else terms
-    t = t.reshape(-1, 64, k, d)
-    acc = np.zeros((64, d))
+    t = t.reshape(-1, LANES, k, d)
+    acc = np.zeros((LANES, d))
     for row in range(t.shape[0]):
         for i in range(k):
             acc = acc + t[row, :, i, :]
-    idx = np.arange(64)
+    idx = np.arange(LANES)
     for s in (32, 16, 8, 4, 2, 1):
         acc = acc + acc[idx ^ s]
-    return acc[0]
+    return (acc[0] + acc[64]) + (acc[128] + acc[192])
 
 
 def _box_nodes(part: Particles, p: int, shape):

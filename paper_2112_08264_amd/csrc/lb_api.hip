@@ -1376,10 +1376,12 @@ lb_status lb1_step(lb1_ctx* ctx, int32_t n) {
           int* own_new = ctx->owner[ctx->ocur ^ 1];
           k1p_step<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, own, ctx->ps, ctx->rho_buf,
                                                                          ctx->g, ctx->c);
-          kp_force_move<ST><<<ctx->np, 64, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g, ctx->c);
+          kp_force_move<ST><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g,
+                                                                       ctx->c);
           kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(own_new, ctx->g.N);
           kp_owner_scatter<<<ctx->np, kBlock, 0, ctx->stream>>>(own_new, ctx->ps, ctx->g);
-          kp_remap<ST><<<ctx->np, 64, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps, ctx->g, ctx->c);
+          kp_remap<ST><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps, ctx->g,
+                                                                  ctx->c);
           LB_HIP(hipGetLastError());
           ctx->cur ^= 1;
           ctx->ocur ^= 1;
@@ -1568,6 +1570,8 @@ lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double m
   ps.box = box;
   ps.radius = radius;
   ps.r2 = radius * radius;
+  ps.near2 = (radius + 1.5) * (radius + 1.5);
+  ps.inner2 = radius > 1.5 ? (radius - 1.5) * (radius - 1.5) : -1.0;
   ps.mass = mass;
   ps.inertia = 0.4 * mass * radius * radius;
   ps.rho0 = ctx->p.rho0[0];

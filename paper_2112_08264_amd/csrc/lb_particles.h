@@ -8,12 +8,12 @@
 //                    W_i = 2 rho w_i (u_b . c_i) / c_s^2, u_b = v + omega x r_b;
 //                    solid nodes get zero populations; fluid nodes with such
 //                    a link record their density for the force pass
-//   kp_force_move    one wave per particle: force and torque summed over its
+//   kp_force_move    one workgroup per particle: force and torque summed over its
 //                    links in float64 in a fixed order, then the leap-frog
 //                    update of velocity, angular velocity and position
 //   kp_owner_fill,
 //   kp_owner_scatter owner map of the new positions (lowest index wins)
-//   kp_remap         one wave per particle: nodes covered by the move hand
+//   kp_remap         one workgroup per particle: nodes covered by the move hand
 //                    their momentum to the particle and are emptied; nodes
 //                    uncovered start at f^eq(rho0, u_b) and take theirs from
 //                    the particle
@@ -23,10 +23,15 @@
 //
 // Fixed summation order of a particle's link and covering sums, so that
 // they are reproducible bit for bit.  The particle's box has S nodes per axis
-// from lo_a = floor(r_a - R) - 1, numbered b = j_x + S (j_y + S j_z).  Lane l
-// of the particle's wave takes b = l, l + 64, ... in order, and at each node
-// directions i = 1..18 in order.  The 64 lane sums are then combined by a
-// butterfly, a_l <- a_l + a_(l xor s) for s = 32, 16, ..., 1.
+// from lo_a = floor(r_a - R) - 1, numbered b = j_x + S (j_y + S j_z).  Thread l
+// of the particle's 256-thread workgroup takes b = l, l + 256, ... in order,
+// and at each node directions i = 1..18 in order.  Each wave combines its 64
+// sums by a butterfly, a_l <- a_l + a_(l xor s) for s = 32, 16, ..., 1; the
+// four wave results give (A_0 + A_1) + (A_2 + A_3).
+//
+// Owner map: the particle index at solid nodes; at fluid nodes kOwnerFluid,
+// or kOwnerNear within R + 1.5 of a centre, so that a fluid node far from
+// every particle (most of them) skips the 18 neighbour lookups.
 #pragma once
 
 #include "lb_fused.h"
@@ -35,6 +40,10 @@
 namespace lbd {
 
 constexpr int kOwnerFluid = 0x7fffffff;
+constexpr int kOwnerNear = 0x7ffffffe;  // fluid, possibly next to a particle
+constexpr int kPartThreads = 256;
+
+__device__ __forceinline__ bool owner_fluid(int o) { return o >= kOwnerNear; }
 
 struct PartState {
   double* pos;     // [P][3], in [0, L)
@@ -44,7 +53,7 @@ struct PartState {
   double* torque;  // [P][3]
   int count;
   int box;         // S = floor(2R) + 4
-  double radius, r2, mass, inertia, rho0;
+  double radius, r2, near2, inner2, mass, inertia, rho0;  // R^2, (R + 1.5)^2, (R - 1.5)^2 or -1
 };
 
 __device__ __forceinline__ int wrap_coord(int c, int L) {
@@ -85,11 +94,13 @@ __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict
   const int b = fused_work_item(blockIdx.x, gridDim.x, gridDim.x);
   const int n = b * kBlock + threadIdx.x;
   if (n >= g.N) return;
-  if (owner[n] != kOwnerFluid) {
+  const int own = owner[n];
+  if (!owner_fluid(own)) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) fout[(long long)i * g.Npad + n] = store_t<ST>(0);
     return;
   }
+  const bool near = own == kOwnerNear;
   int x, y, z;
   node_xyz(n, g, x, y, z);
   int nb[Q];
@@ -114,14 +125,18 @@ __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict
   } else {
     relax_f32(f, fs, rho, ux, uy, uz, coef_om<real>(c, 0), coef_omc<real>(c, 0));
   }
+  int onb[Q];
+  onb[0] = kOwnerFluid;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) onb[i] = near ? owner[nb[i]] : kOwnerFluid;
   bool linked = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     long long dst = (long long)i * g.Npad + nb[i];
     real val = fs[i];
     if (i != 0) {
-      const int p = owner[nb[i]];
-      if (p != kOwnerFluid) {
+      const int p = onb[i];
+      if (!owner_fluid(p)) {
         double rb[3];
         const double W = wall_term(i, x, y, z, static_cast<double>(rho), p, ps, g, rb);
         dst = (long long)OPP[i] * g.Npad + n;
@@ -153,32 +168,64 @@ __device__ __forceinline__ void box_origin(const double* r, double R, int (&lo)[
   for (int a = 0; a < 3; ++a) lo[a] = static_cast<int>(floor(r[a] - R)) - 1;
 }
 
+// The six sums of a particle's workgroup, combined in the fixed order above;
+// valid in thread 0.
+__device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc[d] = wave_sum_xor(acc[d]);
+  if (lane == 0)
+#pragma unroll
+    for (int d = 0; d < 6; ++d) red[wave][d] = acc[d];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int d = 0; d < 6; ++d) acc[d] = (red[0][d] + red[1][d]) + (red[2][d] + red[3][d]);
+}
+
 // Force and torque from the links of the step just made (fnew = f(t+1),
 // owner of step t), then leap-frog: v += F/m, omega += T/I, r += v.
-// One 64-lane workgroup per particle.
+// One 256-thread workgroup per particle.
 template <int ST>
-__global__ void __launch_bounds__(64) kp_force_move(const store_t<ST>* __restrict__ fnew, const int* __restrict__ owner,
-                                                    const double* __restrict__ rho_buf, PartState ps, Geometry g,
-                                                    StepCoeffs c) {
+__global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>* __restrict__ fnew,
+                                                              const int* __restrict__ owner,
+                                                              const double* __restrict__ rho_buf, PartState ps,
+                                                              Geometry g, StepCoeffs c) {
+  __shared__ double red[4][6];
   const int p = blockIdx.x;
-  const int lane = threadIdx.x;
   int lo[3];
   box_origin(ps.pos + 3 * p, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = lane; b < nbox; b += 64) {
+  for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
     if (owner[n] != p) continue;
+    {
+      // nodes deeper than R - 1.5 have only solid neighbours, hence no links
+      const double dx = double(cc[0]) - ps.pos[3 * p], dy = double(cc[1]) - ps.pos[3 * p + 1],
+                   dz = double(cc[2]) - ps.pos[3 * p + 2];
+      if ((dx * dx + dy * dy) + dz * dz < ps.inner2) continue;
+    }
     const int xs = n % g.nx, ys = (n / g.nx) % g.ny, zs = n / (g.nx * g.ny);
+    // All loads of the node's 18 links are issued before any is used (every
+    // address is a valid node); a direction that is not a link adds nothing.
+    int nf[Q], of[Q];
+    double gv[Q], rh[Q];
+#pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int xf = wrap_coord(xs - CX[i], g.nx), yf = wrap_coord(ys - CY[i], g.ny), zf = wrap_coord(zs - CZ[i], g.nz);
-      const int nf = xf + g.nx * (yf + g.ny * zf);
-      if (owner[nf] != kOwnerFluid) continue;
+      nf[i] = wrap_coord(xs - CX[i], g.nx) + g.nx * (wrap_coord(ys - CY[i], g.ny) + g.ny * wrap_coord(zs - CZ[i], g.nz));
+      of[i] = owner[nf[i]];
+      gv[i] = static_cast<double>(decode<ST>(fnew[(long long)OPP[i] * g.Npad + nf[i]], c.shift[0][OPP[i]]));
+      rh[i] = rho_buf[nf[i]];
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (!owner_fluid(of[i])) continue;
+      const int xf = nf[i] % g.nx, yf = (nf[i] / g.nx) % g.ny, zf = nf[i] / (g.nx * g.ny);
       double rb[3];
-      const double W = wall_term(i, xf, yf, zf, rho_buf[nf], p, ps, g, rb);
-      const double gv = static_cast<double>(decode<ST>(fnew[(long long)OPP[i] * g.Npad + nf], c.shift[0][OPP[i]]));
-      const double t = (gv + gv) + W;
+      const double W = wall_term(i, xf, yf, zf, rh[i], p, ps, g, rb);
+      const double t = (gv[i] + gv[i]) + W;
       const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
                            CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
       acc[0] = acc[0] + F[0];
@@ -189,9 +236,8 @@ __global__ void __launch_bounds__(64) kp_force_move(const store_t<ST>* __restric
       acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
     }
   }
-#pragma unroll
-  for (int d = 0; d < 6; ++d) acc[d] = wave_sum_xor(acc[d]);
-  if (lane == 0) {
+  part_reduce(acc, red);
+  if (threadIdx.x == 0) {
     const double L[3] = {double(g.nx), double(g.ny), double(g.nz)};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -213,7 +259,8 @@ __global__ void __launch_bounds__(kBlock) kp_owner_fill(int* __restrict__ owner,
   if (n < N) owner[n] = kOwnerFluid;
 }
 
-// owner[x] = min over particles containing x.  One workgroup per particle.
+// owner[x] = min over particles containing x (kOwnerNear within R + 1.5).
+// One workgroup per particle.
 __global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ owner, PartState ps, Geometry g) {
   const int p = blockIdx.x;
   const double* r = ps.pos + 3 * p;
@@ -224,28 +271,30 @@ __global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ own
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
     const double dx = double(cc[0]) - r[0], dy = double(cc[1]) - r[1], dz = double(cc[2]) - r[2];
-    if ((dx * dx + dy * dy) + dz * dz <= ps.r2) atomicMin(owner + n, p);
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 <= ps.r2) atomicMin(owner + n, p);
+    else if (d2 <= ps.near2) atomicMin(owner + n, kOwnerNear);
   }
 }
 
 // Covering and uncovering after the move; mask follows the new owner map.
 template <int ST>
-__global__ void __launch_bounds__(64) kp_remap(store_t<ST>* __restrict__ f, const int* __restrict__ owner_old,
-                                               const int* __restrict__ owner_new, uint8_t* __restrict__ mask,
-                                               PartState ps, Geometry g, StepCoeffs c) {
+__global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict__ f, const int* __restrict__ owner_old,
+                                                         const int* __restrict__ owner_new, uint8_t* __restrict__ mask,
+                                                         PartState ps, Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
+  __shared__ double red[4][6];
   const int p = blockIdx.x;
-  const int lane = threadIdx.x;
   const double* r = ps.pos + 3 * p;
   int lo[3];
   box_origin(r, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = lane; b < nbox; b += 64) {
+  for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
-    const bool covered = owner_new[n] == p && owner_old[n] == kOwnerFluid;
-    const bool uncovered = owner_old[n] == p && owner_new[n] == kOwnerFluid;
+    const bool covered = owner_new[n] == p && owner_fluid(owner_old[n]);
+    const bool uncovered = owner_old[n] == p && owner_fluid(owner_new[n]);
     if (!covered && !uncovered) continue;
     const double d[3] = {double(cc[0]) - r[0], double(cc[1]) - r[1], double(cc[2]) - r[2]};
     real vals[Q];
@@ -287,9 +336,8 @@ __global__ void __launch_bounds__(64) kp_remap(store_t<ST>* __restrict__ f, cons
     acc[4] = acc[4] + (d[2] * m[0] - d[0] * m[2]);
     acc[5] = acc[5] + (d[0] * m[1] - d[1] * m[0]);
   }
-#pragma unroll
-  for (int dd = 0; dd < 6; ++dd) acc[dd] = wave_sum_xor(acc[dd]);
-  if (lane == 0) {
+  part_reduce(acc, red);
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       ps.vel[3 * p + a] = ps.vel[3 * p + a] + acc[a] / ps.mass;
@@ -304,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) kp_apply_owner(store_t<ST>* __restrict
                                                          uint8_t* __restrict__ mask, Geometry g) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
-  const bool solid = owner[n] != kOwnerFluid;
+  const bool solid = !owner_fluid(owner[n]);
   mask[n] = solid ? 1 : 0;
   if (solid)
 #pragma unroll

@@ -160,3 +160,7 @@ def test_fixed_order_particle_sums_are_sums():
     for d in range(6):
         exact = math.fsum(terms[:, :, d].ravel())
         assert abs(got[d] - exact) <= 64 * 2.0 ** -53 * np.sum(np.abs(terms[:, :, d])) + 1e-300
+    # the grouping is the one documented: a single term lands unchanged, wherever it is
+    one = np.zeros((3375, 18, 6))
+    one[2900, 7, 2] = 1.25
+    assert PT._lane_sum(one)[2] == 1.25
