@@ -200,13 +200,16 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>*
   for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
-    if (owner[n] != p) continue;
     {
-      // nodes deeper than R - 1.5 have only solid neighbours, hence no links
+      // Only the shell R - 1.5 <= |d| <= R can hold this particle's linked
+      // nodes: outside it the node is not the particle's, deeper inside all its
+      // neighbours are solid.  Tested before any load.
       const double dx = double(cc[0]) - ps.pos[3 * p], dy = double(cc[1]) - ps.pos[3 * p + 1],
                    dz = double(cc[2]) - ps.pos[3 * p + 2];
-      if ((dx * dx + dy * dy) + dz * dz < ps.inner2) continue;
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      if (d2 > ps.r2 || d2 < ps.inner2) continue;
     }
+    if (owner[n] != p) continue;
     const int xs = n % g.nx, ys = (n / g.nx) % g.ny, zs = n / (g.nx * g.ny);
     // All loads of the node's 18 links are issued before any is used (every
     // address is a valid node); a direction that is not a link adds nothing.
