@@ -110,5 +110,7 @@ def test_single_fluid_create_rejects_tau_at_or_below_one_half():
 def test_single_fluid_calls_reject_null_context():
     lib = P.library()
     assert lib.lb1_step(None, 1) == P.LB_EINVAL
+    assert lib.lb1_set_particles(None, 1, 2.0, 10.0, None, None, None) == P.LB_EINVAL
+    assert lib.lb1_get_particles(None, None, None, None, None, None) == P.LB_EINVAL
     assert lib.lb1_destroy(None) == P.LB_OK
 
