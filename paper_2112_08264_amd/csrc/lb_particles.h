@@ -68,13 +68,29 @@ __device__ __forceinline__ double fold(double d, double L) {
   return d;
 }
 
+// One particle's centre, velocity and angular velocity, in registers.
+struct PartRegs {
+  double r[3], v[3], w[3];
+};
+
+__device__ __forceinline__ PartRegs part_regs(const PartState& ps, int p) {
+  PartRegs q;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.r[a] = ps.pos[3 * p + a];
+    q.v[a] = ps.vel[3 * p + a];
+    q.w[a] = ps.omg[3 * p + a];
+  }
+  return q;
+}
+
 // W_i and the link midpoint r_b (relative to the particle) for the link
-// from fluid node (x, y, z) in direction i into particle p.
-__device__ __forceinline__ double wall_term(int i, int x, int y, int z, double rho, int p, const PartState& ps,
+// from fluid node (x, y, z) in direction i into the particle q.
+__device__ __forceinline__ double wall_term(int i, int x, int y, int z, double rho, const PartRegs& q,
                                             const Geometry& g, double (&rb)[3]) {
-  const double* r = ps.pos + 3 * p;
-  const double* v = ps.vel + 3 * p;
-  const double* w = ps.omg + 3 * p;
+  const double* r = q.r;
+  const double* v = q.v;
+  const double* w = q.w;
   rb[0] = fold((double(x) + 0.5 * CX[i]) - r[0], double(g.nx));
   rb[1] = fold((double(y) + 0.5 * CY[i]) - r[1], double(g.ny));
   rb[2] = fold((double(z) + 0.5 * CZ[i]) - r[2], double(g.nz));
@@ -129,6 +145,14 @@ __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict
   onb[0] = kOwnerFluid;
 #pragma unroll
   for (int i = 1; i < Q; ++i) onb[i] = near ? owner[nb[i]] : kOwnerFluid;
+  // Nearly always one particle borders the node: its state is loaded once,
+  // after the owner lookups, instead of once per link.
+  int p0 = kOwnerFluid;
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (!owner_fluid(onb[i])) p0 = onb[i];
+  PartRegs q0{};
+  if (p0 != kOwnerFluid) q0 = part_regs(ps, p0);
   bool linked = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -138,7 +162,7 @@ __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict
       const int p = onb[i];
       if (!owner_fluid(p)) {
         double rb[3];
-        const double W = wall_term(i, x, y, z, static_cast<double>(rho), p, ps, g, rb);
+        const double W = wall_term(i, x, y, z, static_cast<double>(rho), p == p0 ? q0 : part_regs(ps, p), g, rb);
         dst = (long long)OPP[i] * g.Npad + n;
         val = fs[i] - static_cast<real>(W);
         linked = true;
@@ -193,8 +217,9 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>*
                                                               Geometry g, StepCoeffs c) {
   __shared__ double red[4][6];
   const int p = blockIdx.x;
+  const PartRegs q = part_regs(ps, p);
   int lo[3];
-  box_origin(ps.pos + 3 * p, ps.radius, lo);
+  box_origin(q.r, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
@@ -204,8 +229,7 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>*
       // Only the shell R - 1.5 <= |d| <= R can hold this particle's linked
       // nodes: outside it the node is not the particle's, deeper inside all its
       // neighbours are solid.  Tested before any load.
-      const double dx = double(cc[0]) - ps.pos[3 * p], dy = double(cc[1]) - ps.pos[3 * p + 1],
-                   dz = double(cc[2]) - ps.pos[3 * p + 2];
+      const double dx = double(cc[0]) - q.r[0], dy = double(cc[1]) - q.r[1], dz = double(cc[2]) - q.r[2];
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       if (d2 > ps.r2 || d2 < ps.inner2) continue;
     }
@@ -227,7 +251,7 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>*
       if (!owner_fluid(of[i])) continue;
       const int xf = nf[i] % g.nx, yf = (nf[i] / g.nx) % g.ny, zf = nf[i] / (g.nx * g.ny);
       double rb[3];
-      const double W = wall_term(i, xf, yf, zf, rh[i], p, ps, g, rb);
+      const double W = wall_term(i, xf, yf, zf, rh[i], q, g, rb);
       const double t = (gv[i] + gv[i]) + W;
       const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
                            CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
