@@ -592,6 +592,10 @@ def main(argv=None) -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "algorithmic_bytes_per_lup": bpl, "lups_per_launch": w.nodes}
+    # attainable bandwidth on this device: a plain 2 GiB device-to-device copy
+    cal = copy_calibration(torch)
+    copy_bw = {"gbs": round(cal["gbs"], 1), "frac_of_peak": round(cal["gbs"] / HBM_PEAK_GBS, 4),
+               "step_frac_of_copy": round(achieved / cal["gbs"], 4)}
 
     forms = {}
     if not args.no_forms and solid is None:
@@ -664,6 +668,7 @@ def main(argv=None) -> int:
         "step_hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
         "fluid_glups": round(glups * (1.0 - solid_fraction), 4),
         "roofline": roofline,
+        "copy_bandwidth": copy_bw,
         "cpu_baseline": cpu,
         "forms": forms,
         "f64_one_ulp_sensitivity": None if accuracy is None else accuracy["f64_one_ulp"],
