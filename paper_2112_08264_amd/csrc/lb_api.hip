@@ -93,6 +93,7 @@ struct lb_ctx {
   int model = LB_MODEL_SHAN_CHEN;
   FusedTiling tiling{};       // the storage's default fused kernel
   FusedTiling tiling_wide{};  // staged float64 kernel on 64 x 4 tiles (nx a multiple of 64)
+  FusedTiling tiling_cg{};    // float32 colour-gradient kernel (64 x 4 tiles)
   int64_t bytes = 0;
 };
 
@@ -263,7 +264,7 @@ void launch_cg_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
     k_fused_pair<ST, false, kFusedTY, false, false, kFusedTX, kModelCG>
         <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr);
   } else if constexpr (ST == ST_F32) {
-    const FusedTiling t = ctx->tiling;
+    const FusedTiling t = ctx->tiling_cg;
     k_fused_pair<ST, false, kFloatTY, false, false, kFloatTX, kModelCG>
         <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
                                                                              nullptr);
@@ -667,14 +668,18 @@ const char* lb_timing_name(int32_t slot) {
 // 1.5% (float32) and 3.5% (float16) and tie for float64.  Lattices that take
 // several rounds anyway use 64-plane chunks: on 512^3 (float32 and float16)
 // they ran 22% faster than whole 512-plane columns.
-bool make_tiling(const lb_params& p, int tile_x, int tile_y, int cus, FusedTiling* out) {
+// chunk_full_round: also use 64-plane chunks when the columns fill exactly
+// one round (the unstaged component-pair kernel of the float32 colour-gradient
+// step runs 17% faster so at 256^3).
+bool make_tiling(const lb_params& p, int tile_x, int tile_y, int cus, FusedTiling* out,
+                 bool chunk_full_round = false) {
   FusedTiling t{};
   t.tiles_x = (p.nx + tile_x - 1) / tile_x;
   t.tiles_y = (p.ny + tile_y - 1) / tile_y;
   const long long cols = static_cast<long long>(t.tiles_x) * t.tiles_y;
   const long long target = cus;
   long long want = (target + cols - 1) / cols;  // chunks wanted
-  if (cols > target) want = p.nz / 64;
+  if (cols > target || (chunk_full_round && cols == target)) want = p.nz / 64;
   if (want < 1) want = 1;
   int chunk = static_cast<int>((p.nz + want - 1) / want);
   if (chunk < 4) chunk = 4;
@@ -751,6 +756,7 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
     const bool f64 = p.storage == LB_F64;
     bool ok = make_tiling(p, f64 ? kFusedTX : kFloatTX, f64 ? kFusedTY : kFloatTY, cus, &ctx->tiling);
     if (ok && f64 && p.nx % kWideTX == 0) ok = make_tiling(p, kWideTX, kWideTY, cus, &ctx->tiling_wide);
+    if (ok && !f64) ok = make_tiling(p, kFloatTX, kFloatTY, cus, &ctx->tiling_cg, true);
     if (!ok) {
       delete ctx;
       return LB_EINVAL;
