@@ -1385,8 +1385,8 @@ lb_status lb1_step(lb1_ctx* ctx, int32_t n) {
           store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
           const int* own = ctx->owner[ctx->ocur];
           int* own_new = ctx->owner[ctx->ocur ^ 1];
-          k1p_step<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, own, ctx->ps, ctx->rho_buf,
-                                                                         ctx->g, ctx->c);
+          k1p_step<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, fout, own, ctx->rho_buf, ctx->g,
+                                                                         ctx->c);
           kp_force_move<ST><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g,
                                                                        ctx->c);
           kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(own_new, ctx->g.N);

@@ -3,13 +3,13 @@
 // LADDFLBE, FORCEPP, FORCEPARTEQ, TORQUEPARTEQ), HIP kernels.
 //
 // One step, t -> t + 1 (each line one launch):
-//   k1p_step         collide fluid nodes, push; links into a particle bounce
-//                    back with the moving-wall correction
-//                    W_i = 2 rho w_i (u_b . c_i) / c_s^2, u_b = v + omega x r_b;
-//                    solid nodes get zero populations; fluid nodes with such
-//                    a link record their density for the force pass
-//   kp_force_move    one workgroup per particle: force and torque summed over its
-//                    links in float64 in a fixed order, then the leap-frog
+//   k1p_step         collide fluid nodes and push every population, solid
+//                    nodes push zeros; fluid nodes near a particle record
+//                    their density
+//   kp_force_move    one workgroup per particle: bounce-back at its links with
+//                    the moving-wall correction W_i = 2 rho w_i (u_b . c_i) / c_s^2,
+//                    u_b = v + omega x r_b; force and torque summed over the
+//                    links in float64 in a fixed order; then the leap-frog
 //                    update of velocity, angular velocity and position
 //   kp_owner_fill,
 //   kp_owner_scatter owner map of the new positions (lowest index wins)
@@ -30,8 +30,8 @@
 // four wave results give (A_0 + A_1) + (A_2 + A_3).
 //
 // Owner map: the particle index at solid nodes; at fluid nodes kOwnerFluid,
-// or kOwnerNear within R + 1.5 of a centre, so that a fluid node far from
-// every particle (most of them) skips the 18 neighbour lookups.
+// or kOwnerNear within R + 1.5 of a centre (every fluid end of a link lies
+// within R + sqrt 2), where the fluid kernel records the density.
 #pragma once
 
 #include "lb_fused.h"
@@ -42,6 +42,7 @@ namespace lbd {
 constexpr int kOwnerFluid = 0x7fffffff;
 constexpr int kOwnerNear = 0x7ffffffe;  // fluid, possibly next to a particle
 constexpr int kPartThreads = 256;
+constexpr int kLinkChunk = 6;  // directions whose link loads are in flight together (divides 18)
 
 __device__ __forceinline__ bool owner_fluid(int o) { return o >= kOwnerNear; }
 
@@ -102,25 +103,30 @@ __device__ __forceinline__ double wall_term(int i, int x, int y, int z, double r
 }
 
 // Single-fluid step with particles.  One work-item per node, as k1_step.
+// Every node pushes all 19 populations without looking at its neighbours:
+// a fluid node its post-collision values, a solid node zeros.  A population
+// pushed into a particle node therefore waits in that node's slot, and the
+// slot of the fluid node it should bounce back into holds the zero its solid
+// neighbour pushed; kp_force_move turns each such pair into the bounce-back
+// with the moving-wall term.  Each slot has one writer.  Fluid nodes near a
+// particle (kOwnerNear) record their density for that pass.
 template <int ST>
 __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
-                                                   const int* __restrict__ owner, PartState ps,
-                                                   double* __restrict__ rho_buf, Geometry g, StepCoeffs c) {
+                                                   const int* __restrict__ owner, double* __restrict__ rho_buf,
+                                                   Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
   const int b = fused_work_item(blockIdx.x, gridDim.x, gridDim.x);
   const int n = b * kBlock + threadIdx.x;
   if (n >= g.N) return;
   const int own = owner[n];
-  if (!owner_fluid(own)) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) fout[(long long)i * g.Npad + n] = store_t<ST>(0);
-    return;
-  }
-  const bool near = own == kOwnerNear;
   int x, y, z;
   node_xyz(n, g, x, y, z);
   int nb[Q];
   neighbours(x, y, z, g, nb);
+  // Solid nodes hold zero populations; they go through the same arithmetic
+  // (0/0 included) and store zeros in the same store instructions as the
+  // fluid nodes of their wave.
+  const bool solid = !owner_fluid(own);
   real f[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = decode<ST>(fin[(long long)i * g.Npad + n], c.shift[0][i]);
@@ -141,36 +147,10 @@ __global__ void __launch_bounds__(kBlock) k1p_step(const store_t<ST>* __restrict
   } else {
     relax_f32(f, fs, rho, ux, uy, uz, coef_om<real>(c, 0), coef_omc<real>(c, 0));
   }
-  int onb[Q];
-  onb[0] = kOwnerFluid;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) onb[i] = near ? owner[nb[i]] : kOwnerFluid;
-  // Nearly always one particle borders the node: its state is loaded once,
-  // after the owner lookups, instead of once per link.
-  int p0 = kOwnerFluid;
-#pragma unroll
-  for (int i = 1; i < Q; ++i)
-    if (!owner_fluid(onb[i])) p0 = onb[i];
-  PartRegs q0{};
-  if (p0 != kOwnerFluid) q0 = part_regs(ps, p0);
-  bool linked = false;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    long long dst = (long long)i * g.Npad + nb[i];
-    real val = fs[i];
-    if (i != 0) {
-      const int p = onb[i];
-      if (!owner_fluid(p)) {
-        double rb[3];
-        const double W = wall_term(i, x, y, z, static_cast<double>(rho), p == p0 ? q0 : part_regs(ps, p), g, rb);
-        dst = (long long)OPP[i] * g.Npad + n;
-        val = fs[i] - static_cast<real>(W);
-        linked = true;
-      }
-    }
-    fout[dst] = encode<ST>(val, c.shift[0][i]);  // w_opp(i) = w_i: same float16 offset
-  }
-  if (linked) rho_buf[n] = static_cast<double>(rho);
+  for (int i = 0; i < Q; ++i)
+    fout[(long long)i * g.Npad + nb[i]] = solid ? store_t<ST>(0) : encode<ST>(fs[i], c.shift[0][i]);
+  if (own == kOwnerNear) rho_buf[n] = static_cast<double>(rho);
 }
 
 __device__ __forceinline__ double wave_sum_xor(double v) {
@@ -207,14 +187,19 @@ __device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6
     for (int d = 0; d < 6; ++d) acc[d] = (red[0][d] + red[1][d]) + (red[2][d] + red[3][d]);
 }
 
-// Force and torque from the links of the step just made (fnew = f(t+1),
-// owner of step t), then leap-frog: v += F/m, omega += T/I, r += v.
-// One 256-thread workgroup per particle.
+// Bounce-back at the particle's links, then force and torque from them,
+// then leap-frog: v += F/m, omega += T/I, r += v.  One 256-thread workgroup
+// per particle, on fnew just pushed by k1p_step (owner of step t).  For the
+// link from fluid node x_f into the particle's node x_s = x_f + c_i, slot i
+// of x_s holds f*_i(x_f); it becomes f_ibar(x_f, t+1) = f*_i(x_f) - W_i and
+// the slot is cleared.  Every link of a node belongs to its owner, so each
+// slot is touched by one workgroup.
 template <int ST>
-__global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>* __restrict__ fnew,
+__global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __restrict__ fnew,
                                                               const int* __restrict__ owner,
                                                               const double* __restrict__ rho_buf, PartState ps,
                                                               Geometry g, StepCoeffs c) {
+  using real = real_t<ST>;
   __shared__ double red[4][6];
   const int p = blockIdx.x;
   const PartRegs q = part_regs(ps, p);
@@ -235,32 +220,44 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(const store_t<ST>*
     }
     if (owner[n] != p) continue;
     const int xs = n % g.nx, ys = (n / g.nx) % g.ny, zs = n / (g.nx * g.ny);
-    // All loads of the node's 18 links are issued before any is used (every
-    // address is a valid node); a direction that is not a link adds nothing.
-    int nf[Q], of[Q];
-    double gv[Q], rh[Q];
+    // Directions in chunks of kLinkChunk, in order: the loads of a chunk are
+    // issued before any is used (every address is a valid node), and the
+    // registers of one chunk, not of all 18, stay live.  A direction that is
+    // not a link adds nothing.
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      nf[i] = wrap_coord(xs - CX[i], g.nx) + g.nx * (wrap_coord(ys - CY[i], g.ny) + g.ny * wrap_coord(zs - CZ[i], g.nz));
-      of[i] = owner[nf[i]];
-      gv[i] = static_cast<double>(decode<ST>(fnew[(long long)OPP[i] * g.Npad + nf[i]], c.shift[0][OPP[i]]));
-      rh[i] = rho_buf[nf[i]];
-    }
+    for (int i0 = 1; i0 < Q; i0 += kLinkChunk) {
+      int nf[kLinkChunk], of[kLinkChunk];
+      real pushed[kLinkChunk];
+      double rh[kLinkChunk];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (!owner_fluid(of[i])) continue;
-      const int xf = nf[i] % g.nx, yf = (nf[i] / g.nx) % g.ny, zf = nf[i] / (g.nx * g.ny);
-      double rb[3];
-      const double W = wall_term(i, xf, yf, zf, rh[i], q, g, rb);
-      const double t = (gv[i] + gv[i]) + W;
-      const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
-                           CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
-      acc[0] = acc[0] + F[0];
-      acc[1] = acc[1] + F[1];
-      acc[2] = acc[2] + F[2];
-      acc[3] = acc[3] + (rb[1] * F[2] - rb[2] * F[1]);
-      acc[4] = acc[4] + (rb[2] * F[0] - rb[0] * F[2]);
-      acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
+      for (int k = 0; k < kLinkChunk; ++k) {
+        const int i = i0 + k;
+        nf[k] = wrap_coord(xs - CX[i], g.nx) + g.nx * (wrap_coord(ys - CY[i], g.ny) + g.ny * wrap_coord(zs - CZ[i], g.nz));
+        of[k] = owner[nf[k]];
+        pushed[k] = decode<ST>(fnew[(long long)i * g.Npad + n], c.shift[0][i]);
+        rh[k] = rho_buf[nf[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kLinkChunk; ++k) {
+        const int i = i0 + k;
+        if (!owner_fluid(of[k])) continue;
+        const int xf = nf[k] % g.nx, yf = (nf[k] / g.nx) % g.ny, zf = nf[k] / (g.nx * g.ny);
+        double rb[3];
+        const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
+        const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[0][i]);  // w_opp(i) = w_i
+        fnew[(long long)OPP[i] * g.Npad + nf[k]] = back;
+        fnew[(long long)i * g.Npad + n] = store_t<ST>(0);
+        const double gv = static_cast<double>(decode<ST>(back, c.shift[0][i]));
+        const double t = (gv + gv) + W;
+        const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
+                             CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
+        acc[0] = acc[0] + F[0];
+        acc[1] = acc[1] + F[1];
+        acc[2] = acc[2] + F[2];
+        acc[3] = acc[3] + (rb[1] * F[2] - rb[2] * F[1]);
+        acc[4] = acc[4] + (rb[2] * F[0] - rb[0] * F[2]);
+        acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
+      }
     }
   }
   part_reduce(acc, red);
