@@ -56,11 +56,15 @@ Fixed order of the float64 particle sums (so that a GPU running one
 
 * Each particle's box has S = floor(2R) + 4 nodes per axis, from
   lo_a = floor(r_pa - R) - 1.  Box nodes are numbered b = j_x + S (j_y + S j_z).
-* For the link sums, 256 partial sums are formed.  Partial l takes box nodes
-  b = l, l + 256, ... in order; at each node it takes directions i = 1..18 in
-  order, adding F_i and r_b x F_i of every link from a fluid node into that
-  node (solid, of this particle).  For the covering sums it adds each node's
-  single term.
+* 256 partial sums are formed over a list of box nodes in increasing b:
+  partial l takes the list's entries l, l + 256, ... in order.
+  * Link sums: the list is the shell, the box nodes with
+    (R - 1.5)^2 <= (d_x d_x + d_y d_y) + d_z d_z <= R^2, d = node - r_p (a
+    node of the particle deeper in has all 18 neighbours inside it).  At each
+    entry the partial takes directions i = 1..18 in order, adding F_i and
+    r_b x F_i of every link from a fluid node into that node, if the node is
+    this particle's.
+  * Covering sums: the list is the whole box; each node adds its single term.
 * The partials are combined in four groups of 64 (l = 64 w .. 64 w + 63), each
   by a butterfly: for s = 32, 16, ..., 1, a_l <- a_l + a_(l xor s).  The
   group results A_0..A_3 (at l = 64 w) give (A_0 + A_1) + (A_2 + A_3).
@@ -248,8 +252,14 @@ def link_forces(fnew: np.ndarray, rho: np.ndarray, part: Particles, owner: np.nd
     P = part.pos.shape[0]
     F = np.zeros((P, 3))
     T = np.zeros((P, 3))
+    R2 = part.radius * part.radius
+    inner2 = (part.radius - 1.5) * (part.radius - 1.5) if part.radius > 1.5 else -1.0
     for p in range(P):
         (cx, cy, cz), (zw, yw, xw) = _box_nodes(part, p, shape)
+        dx, dy, dz = cx - part.pos[p, 0], cy - part.pos[p, 1], cz - part.pos[p, 2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        shell = np.nonzero((d2 <= R2) & (d2 >= inner2))[0]  # increasing b
+        cx, cy, cz, zw, yw, xw = cx[shell], cy[shell], cz[shell], zw[shell], yw[shell], xw[shell]
         mine = owner[zw, yw, xw] == p
         terms = np.zeros((cx.size, Q - 1, 6))
         for i in range(1, Q):

@@ -57,10 +57,15 @@ struct PartState {
   double radius, r2, near2, inner2, mass, inertia, rho0;  // R^2, (R + 1.5)^2, (R - 1.5)^2 or -1
 };
 
+// Periodic wrap of any coordinate (a box of a particle whose state has gone
+// non-finite still addresses the lattice).
 __device__ __forceinline__ int wrap_coord(int c, int L) {
   c %= L;
   return c < 0 ? c + L : c;
 }
+
+// Periodic wrap of a coordinate in [-1, L], a neighbour of a wrapped one.
+__device__ __forceinline__ int wrap_step(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
 // Nearest periodic image of a coordinate difference.
 __device__ __forceinline__ double fold(double d, double L) {
@@ -194,6 +199,12 @@ __device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6
 // of x_s holds f*_i(x_f); it becomes f_ibar(x_f, t+1) = f*_i(x_f) - W_i and
 // the slot is cleared.  Every link of a node belongs to its owner, so each
 // slot is touched by one workgroup.
+//
+// Only the shell R - 1.5 <= |d| <= R of the box can hold linked nodes of the
+// particle (a node deeper in has all its neighbours inside).  The shell nodes
+// are queued in LDS in box order, 256 at a time, so that every thread works
+// on one (a seventh or so of the box); thread l takes queue entries
+// l, l + 256, ..., which is the fixed order above.
 template <int ST>
 __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __restrict__ fnew,
                                                               const int* __restrict__ owner,
@@ -201,29 +212,26 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
                                                               Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
   __shared__ double red[4][6];
+  __shared__ int queue[2 * kPartThreads];
+  __shared__ int wave_count[kPartThreads / 64];
   const int p = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const PartRegs q = part_regs(ps, p);
   int lo[3];
   box_origin(q.r, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
+
+  // The links of shell node b, directions in chunks of kLinkChunk, in order.
+  // A chunk issues its owner loads together, then the pushed value and the
+  // density of its fluid neighbours only (about a quarter of a shell node's
+  // neighbours are fluid), so that the registers of one chunk, not of all 18,
+  // stay live.  A direction that is not a link adds nothing.
+  auto links = [&](int b) {
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
-    {
-      // Only the shell R - 1.5 <= |d| <= R can hold this particle's linked
-      // nodes: outside it the node is not the particle's, deeper inside all its
-      // neighbours are solid.  Tested before any load.
-      const double dx = double(cc[0]) - q.r[0], dy = double(cc[1]) - q.r[1], dz = double(cc[2]) - q.r[2];
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (d2 > ps.r2 || d2 < ps.inner2) continue;
-    }
-    if (owner[n] != p) continue;
-    const int xs = n % g.nx, ys = (n / g.nx) % g.ny, zs = n / (g.nx * g.ny);
-    // Directions in chunks of kLinkChunk, in order: the loads of a chunk are
-    // issued before any is used (every address is a valid node), and the
-    // registers of one chunk, not of all 18, stay live.  A direction that is
-    // not a link adds nothing.
+    if (owner[n] != p) return;
+    const int xs = wrap_coord(cc[0], g.nx), ys = wrap_coord(cc[1], g.ny), zs = wrap_coord(cc[2], g.nz);
 #pragma unroll
     for (int i0 = 1; i0 < Q; i0 += kLinkChunk) {
       int nf[kLinkChunk], of[kLinkChunk];
@@ -232,16 +240,24 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
 #pragma unroll
       for (int k = 0; k < kLinkChunk; ++k) {
         const int i = i0 + k;
-        nf[k] = wrap_coord(xs - CX[i], g.nx) + g.nx * (wrap_coord(ys - CY[i], g.ny) + g.ny * wrap_coord(zs - CZ[i], g.nz));
+        nf[k] = wrap_step(xs - CX[i], g.nx) + g.nx * (wrap_step(ys - CY[i], g.ny) + g.ny * wrap_step(zs - CZ[i], g.nz));
         of[k] = owner[nf[k]];
-        pushed[k] = decode<ST>(fnew[(long long)i * g.Npad + n], c.shift[0][i]);
-        rh[k] = rho_buf[nf[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kLinkChunk; ++k) {
+        const int i = i0 + k;
+        pushed[k] = real(0);
+        rh[k] = 0.0;
+        if (owner_fluid(of[k])) {
+          pushed[k] = decode<ST>(fnew[(long long)i * g.Npad + n], c.shift[0][i]);
+          rh[k] = rho_buf[nf[k]];
+        }
       }
 #pragma unroll
       for (int k = 0; k < kLinkChunk; ++k) {
         const int i = i0 + k;
         if (!owner_fluid(of[k])) continue;
-        const int xf = nf[k] % g.nx, yf = (nf[k] / g.nx) % g.ny, zf = nf[k] / (g.nx * g.ny);
+        const int xf = wrap_step(xs - CX[i], g.nx), yf = wrap_step(ys - CY[i], g.ny), zf = wrap_step(zs - CZ[i], g.nz);
         double rb[3];
         const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
         const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[0][i]);  // w_opp(i) = w_i
@@ -259,7 +275,40 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
         acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
       }
     }
+  };
+
+  int pending = 0;  // queued shell nodes, the same in every thread (below 256 between rounds)
+  for (int b0 = 0; b0 < nbox; b0 += kPartThreads) {
+    const int b = b0 + threadIdx.x;
+    bool shell = false;
+    if (b < nbox) {
+      int cc[3];
+      box_node(b, lo, S, g, cc);
+      const double dx = double(cc[0]) - q.r[0], dy = double(cc[1]) - q.r[1], dz = double(cc[2]) - q.r[2];
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      shell = d2 <= ps.r2 && d2 >= ps.inner2;
+    }
+    const unsigned long long m = __ballot(shell);
+    if (lane == 0) wave_count[wave] = __popcll(m);
+    __syncthreads();
+    int slot = pending, total = 0;
+#pragma unroll
+    for (int w = 0; w < kPartThreads / 64; ++w) {
+      slot += w < wave ? wave_count[w] : 0;
+      total += wave_count[w];
+    }
+    if (shell) queue[slot + __popcll(m & ((1ull << lane) - 1ull))] = b;  // slot + rank < 2 * 256
+    pending += total;
+    __syncthreads();
+    if (pending >= kPartThreads) {
+      links(queue[threadIdx.x]);
+      __syncthreads();  // every thread has read its entry
+      if (threadIdx.x < pending - kPartThreads) queue[threadIdx.x] = queue[kPartThreads + threadIdx.x];
+      pending -= kPartThreads;
+      __syncthreads();
+    }
   }
+  if (threadIdx.x < pending) links(queue[threadIdx.x]);
   part_reduce(acc, red);
   if (threadIdx.x == 0) {
     const double L[3] = {double(g.nx), double(g.ny), double(g.nz)};
