@@ -18,6 +18,8 @@ from oracle import lb_particles as PT
 from oracle import lb_single as S
 import synth
 
+import particle_window as PW
+
 pytestmark = pytest.mark.gpu
 
 
@@ -215,43 +217,21 @@ def test_full_size_case3c_conserves_momentum(name):
     assert np.all(pos >= 0.0) and np.all(pos < 256.0)
 
 
-def _isolated(centres, radius, reach, count, seed):
-    """Indices of up to ``count`` particles (seeded choice) with no other
-    centre within ``reach`` (minimum image on the 256^3 box) and every
-    coordinate in [32, 240]."""
-    box = 256.0
-    d = centres[:, None, :] - centres[None, :, :]
-    d -= box * np.round(d / box)
-    d2 = np.einsum("ijk,ijk->ij", d, d)
-    np.fill_diagonal(d2, np.inf)
-    inner = np.all((centres >= 32.0) & (centres <= 240.0), axis=1)
-    iso = np.nonzero((d2.min(axis=1) > reach * reach) & inner)[0]
-    rng = np.random.default_rng(seed)
-    return np.sort(rng.choice(iso, size=min(count, iso.size), replace=False))
-
 
 @pytest.mark.parametrize("name", ["case3c_256_f64", "case3c_256_f32"])
 def test_full_size_case3c_sampled_one_step(name):
     """The 10% moving-sphere workload (2407 spheres, 256^3) as the benchmark
-    launches it, one step, checked particle by particle.  For each sampled
-    particle (no other centre within 2R + 5, every coordinate in [32, 240])
-    the oracle steps a 32^3 periodic window centred on it.
-
-    The populations compared lie within R + 3 of the centre.  They, the
-    particle's links and its covering depend only on nodes within
-    R + 3 + sqrt 2, which no other particle and no end of the window reaches.
-    The particle's box stays clear of the lattice's periodic ends, so the
-    shift to the window and every coordinate difference are exact in both
-    frames: float64 force, torque, position, velocities and populations are
-    compared bit for bit.  The move itself is taken in the lattice's own
-    frame, where the position's rounding lives.  (Wrapped coordinates of a
-    particle across the periodic ends round differently from a window's; the
-    small-box tests cover those against the whole-lattice oracle.)"""
+    launches it, one step, checked sphere by sphere: 8 sampled spheres
+    against the oracle stepped on a 32^3 window around each (the window
+    reduction and its exactness are described in ``particle_window``).
+    float64 force, torque, position, velocities and the populations within
+    R + 3 of the centre are compared bit for bit.  Spheres across the
+    periodic ends are covered by the small-box tests, against the
+    whole-lattice oracle."""
     torch = _torch()
     w = synth.WORKLOADS[name]
     _say(f"case {w.name} sampled one step")
     shape = w.shape
-    nz, ny, nx = shape
     n = w.nodes
     rho, _ = synth.fluid_fields(shape, w.amp, w.seed)
     centres = synth.sphere_centres(shape, w.spheres, w.radius, w.sphere_seed)
@@ -259,7 +239,7 @@ def test_full_size_case3c_sampled_one_step(name):
     vel = rng.uniform(-0.03, 0.03, (w.spheres, 3))
     omg = rng.uniform(-0.003, 0.003, (w.spheres, 3))
     mass = synth.particle_mass(w.radius)
-    sample = _isolated(centres, w.radius, 2.0 * w.radius + 5.0, 8, 59)
+    sample = PW.isolated(centres, w.radius, shape, 8, 59)
     assert sample.size == 8
     with P.SingleFluid(shape, tau=w.tau[0], storage=w.storage) as lat:
         lat.set_fields(rho.ravel().copy())
@@ -270,43 +250,24 @@ def test_full_size_case3c_sampled_one_step(name):
         pos, v1, w1, force, torque = lat.particles()
         torch.cuda.synchronize()
     f = f.view(19, n)
-    W = 32
-    j = np.arange(W)
-    zw, yw, xw = np.meshgrid(j, j, j, indexing="ij")
     errs = []
     for p in sample:
-        o = np.floor(centres[p]).astype(np.int64) - W // 2
-        zi, yi, xi = np.meshgrid((o[2] + j) % nz, (o[1] + j) % ny, (o[0] + j) % nx, indexing="ij")
-        here = PT.Particles(w.radius, mass, [centres[p] - o], [vel[p]], [omg[p]])
-        f0, own0 = PT.init(rho[zi, yi, xi], here)
-        fw, rw = PT.fluid_step(f0, w.tau[0], here, own0)
-        F, T = PT.link_forces(fw, rw, here, own0)
-        moved = PT.move(PT.Particles(w.radius, mass, [centres[p]], [vel[p]], [omg[p]]), F, T, shape)
-        d = moved.pos[0] - o
-        there = PT.Particles(w.radius, mass, [d], moved.vel, moved.omg)
-        fw = PT.remap(fw, there, own0, PT.owner_map((W, W, W), there), 1.0)
-        # window nodes within R + 3 of the particle: its links' fluid ends (R + sqrt 2), its covering and more
-        c = centres[p] - o
-        near = ((xw - c[0]) ** 2 + (yw - c[1]) ** 2) + (zw - c[2]) ** 2 <= (w.radius + 3.0) ** 2
-        bz, by, bx = zw[near], yw[near], xw[near]
-        ref = fw[:, bz, by, bx]
-        idx = torch.from_numpy((((bz + o[2]) % nz * ny + (by + o[1]) % ny) * nx + (bx + o[0]) % nx).ravel())
-        got = f[:, idx.to("cuda")].cpu().numpy()
+        F, T, r1, vr, wr, ref, idx = PW.step_window(rho, w.tau[0], w.radius, mass, centres[p], vel[p], omg[p], shape)
+        got = f[:, torch.from_numpy(idx).to("cuda")].cpu().numpy()
         if w.storage == "f64":
-            assert np.array_equal(force[p], F[0]), p
-            assert np.array_equal(torque[p], T[0]), p
-            assert np.array_equal(pos[p], moved.pos[0]), p
-            assert np.array_equal(v1[p], there.vel[0]), p
-            assert np.array_equal(w1[p], there.omg[0]), p
+            assert np.array_equal(force[p], F), p
+            assert np.array_equal(torque[p], T), p
+            assert np.array_equal(pos[p], r1), p
+            assert np.array_equal(v1[p], vr), p
+            assert np.array_equal(w1[p], wr), p
             assert np.array_equal(got, ref), p
         else:
             # A sphere of radius 5.5 has about 2200 links.  Each adds 2 g, g a float32 population near 1/18
             # carrying a few float32 roundings (about 1e-8 each).  A random walk over them gives about 1e-6, and
             # the 18 links of one fluid node share that node's collision, so their errors need not cancel: the
             # bounds allow 20 times the walk.  Torque arms reach R + 1; v and omega divide by m and I.
-            errs.append([np.max(np.abs(force[p] - F[0])), np.max(np.abs(torque[p] - T[0])),
-                         np.max(np.abs(pos[p] - moved.pos[0])), np.max(np.abs(v1[p] - there.vel[0])),
-                         np.max(np.abs(w1[p] - there.omg[0])), np.max(np.abs(got - ref))])
+            errs.append([np.max(np.abs(force[p] - F)), np.max(np.abs(torque[p] - T)), np.max(np.abs(pos[p] - r1)),
+                         np.max(np.abs(v1[p] - vr)), np.max(np.abs(w1[p] - wr)), np.max(np.abs(got - ref))])
     if errs:
         e = np.max(np.array(errs), axis=0)
         _say("  max |dF| {:.1e} |dT| {:.1e} |dpos| {:.1e} |dv| {:.1e} |domega| {:.1e} |df| {:.1e}".format(*e))

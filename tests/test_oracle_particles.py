@@ -10,6 +10,7 @@ import pytest
 from oracle import lb_oracle as O
 from oracle import lb_particles as PT
 from oracle import lb_single as S
+import synth
 
 
 def _fluid(shape, seed, amp=0.01, vel=0.01):
@@ -164,3 +165,32 @@ def test_fixed_order_particle_sums_are_sums():
     one = np.zeros((3375, 18, 6))
     one[2900, 7, 2] = 1.25
     assert PT._lane_sum(one)[2] == 1.25
+
+
+def test_window_step_equals_the_whole_lattice_step():
+    """Locality and exact translation of the particle step: for spheres far
+    from every other sphere and from the lattice's ends, one oracle step of a
+    32^3 window around the sphere gives the whole-lattice step's force,
+    torque, position, velocities and nearby populations bit for bit (the
+    full-size GPU check relies on this).  96^3, 40 spheres of radius 5.5."""
+    import particle_window as PW
+    L = 96
+    shape = (L, L, L)
+    R = 5.5
+    centres = synth.sphere_centres(shape, 40, R, 3)
+    rng = np.random.default_rng(58)
+    vel = rng.uniform(-0.03, 0.03, (40, 3))
+    omg = rng.uniform(-0.003, 0.003, (40, 3))
+    mass = synth.particle_mass(R)
+    rho, _ = synth.fluid_fields(shape, 0.02, 11)
+    part = PT.Particles(R, mass, centres, vel, omg)
+    f, owner = PT.init(rho, part)
+    f1, q, _ = PT.step(f, 1.0, part.copy(), owner, n=1)
+    f1 = f1.reshape(19, -1)
+    sample = PW.isolated(centres, R, shape, 8, 0)
+    assert sample.size >= 3
+    for p in sample:
+        F, T, r1, v1, w1, fw, idx = PW.step_window(rho, 1.0, R, mass, centres[p], vel[p], omg[p], shape)
+        assert np.array_equal(F, q.force[p]) and np.array_equal(T, q.torque[p]), p
+        assert np.array_equal(r1, q.pos[p]) and np.array_equal(v1, q.vel[p]) and np.array_equal(w1, q.omg[p]), p
+        assert np.array_equal(fw, f1[:, idx]), p
