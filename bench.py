@@ -269,7 +269,10 @@ def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool
     single-fluid step on 256^3: the paper's case-3 volume fractions 0.1%, 1%
     and 10%, float32 (and float64 at 10%).  GLUPS count every node; the
     overhead is the time per step over that of the same lattice without
-    particles."""
+    particles; hbm_frac_fluid prices the step at the fluid's own bytes (19
+    populations each way and the owner word per node) against 8 TB/s, a
+    lower bound of its traffic that leaves out the particle kernels'
+    scattered accesses."""
     import numpy as np
 
     out = {"lattice": [256, 256, 256], "radius": 5.5,
@@ -308,9 +311,12 @@ def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool
         finally:
             lat.close()
         phi = w.spheres * (4.0 / 3.0) * np.pi * w.radius ** 3 / w.nodes
+        # fluid bytes per node: 19 populations read and written, plus the owner word
+        bpl = 2 * 19 * (4 if w.storage == "f32" else 8) + 4
         out[name] = {"spheres": w.spheres, "volume_fraction": round(phi, 5), "glups": round(w.nodes / (ms * 1e-3) / 1e9, 4),
                      "ms_per_step": round(ms, 4), "no_particles_ms_per_step": round(base[w.storage], 4),
-                     "overhead": round(ms / base[w.storage] - 1.0, 4), "nonfinite": nonfinite}
+                     "overhead": round(ms / base[w.storage] - 1.0, 4), "fluid_bytes_per_lup": bpl,
+                     "hbm_frac_fluid": round(bpl * w.nodes / (ms * 1e-3) / 8e12, 4), "nonfinite": nonfinite}
     if cpu:
         from oracle import lb_particles as PT
 

@@ -223,10 +223,12 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
   // The links of shell node b, directions in chunks of kLinkChunk, in order.
-  // A chunk issues its owner loads together, then the pushed value and the
-  // density of its fluid neighbours only (about a quarter of a shell node's
-  // neighbours are fluid), so that the registers of one chunk, not of all 18,
-  // stay live.  A direction that is not a link adds nothing.
+  // A neighbour x_s - c_i inside this particle (the owner map's own test, on
+  // the same unwrapped coordinates, so the same decision) is solid; only the
+  // others (about a quarter of a shell node's neighbours) load their owner,
+  // the pushed value and their density, all at once.  The registers of one
+  // chunk, not of all 18, stay live.  A direction that is not a link adds
+  // nothing.
   auto links = [&](int b) {
     int cc[3];
     const int n = box_node(b, lo, S, g, cc);
@@ -240,15 +242,15 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
 #pragma unroll
       for (int k = 0; k < kLinkChunk; ++k) {
         const int i = i0 + k;
+        const double ex = double(cc[0] - CX[i]) - q.r[0], ey = double(cc[1] - CY[i]) - q.r[1],
+                     ez = double(cc[2] - CZ[i]) - q.r[2];
+        const bool outside = (ex * ex + ey * ey) + ez * ez > ps.r2;
         nf[k] = wrap_step(xs - CX[i], g.nx) + g.nx * (wrap_step(ys - CY[i], g.ny) + g.ny * wrap_step(zs - CZ[i], g.nz));
-        of[k] = owner[nf[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < kLinkChunk; ++k) {
-        const int i = i0 + k;
+        of[k] = p;  // solid
         pushed[k] = real(0);
         rh[k] = 0.0;
-        if (owner_fluid(of[k])) {
+        if (outside) {
+          of[k] = owner[nf[k]];
           pushed[k] = decode<ST>(fnew[(long long)i * g.Npad + n], c.shift[0][i]);
           rh[k] = rho_buf[nf[k]];
         }

@@ -64,6 +64,13 @@ CASES = {
     "wrap": ((19, 21, 24), PT.Particles(2.7, 250.0, [[0.4, 10.2, 18.7], [22.9, 20.6, 3.3], [12.0, 5.5, 9.9]],
                                         [[-0.12, 0.03, 0.09], [0.1, 0.11, -0.04], [0.0, 0.1, 0.0]],
                                         [[0.01, 0.02, -0.01], [0.0, 0.0, 0.0], [-0.02, 0.0, 0.03]])),
+    # two spheres under one node apart: fluid nodes between them have links into both
+    "close": ((16, 18, 28), PT.Particles(3.3, 400.0, [[8.2, 9.1, 8.4], [15.6, 9.4, 8.0]],
+                                         [[0.03, 0.0, 0.01], [-0.03, 0.01, 0.0]],
+                                         [[0.0, 0.01, 0.0], [0.01, 0.0, -0.01]])),
+    # two overlapping spheres: nodes inside both belong to the lower index
+    "overlap": ((18, 18, 22), PT.Particles(3.1, 400.0, [[9.3, 8.8, 9.1], [13.4, 9.6, 9.0]],
+                                           [[0.02, 0.0, 0.0], [0.02, 0.01, 0.0]], None)),
 }
 
 
