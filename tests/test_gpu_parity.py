@@ -381,3 +381,27 @@ def test_full_size_reduced_storage_sampled_one_step(wname):
         assert ratio <= 1.0, (x, y, z, ratio)
     _say(f"  worst error / bound {worst:.3f} over {len(sites)} sites")
 
+
+
+def test_f32_tall_tiles_equal_the_64x4_tiles_bitwise():
+    """float32 without solids runs 64 x 8 tiles where their columns keep
+    chunks of at least 64 planes; the node arithmetic does not depend on the
+    tile, so the result equals, bit for bit, the 64 x 4 kernel's (run here
+    through an all-fluid solid mask).  128 x 1020 x 64: 256 columns of 64 x 8
+    with a ragged last tile row, one 64-plane chunk each."""
+    torch = _torch()
+    shape = (64, 1020, 128)
+    n = int(np.prod(shape))
+    _say(f"case f32 tall tiles vs 64x4 shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.02, 23)
+    out = []
+    for solid in (None, np.zeros(n, dtype=np.uint8)):
+        with P.Lattice(shape, tau=(0.8, 0.9), G=3.5, storage="f32") as lat:
+            lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy(), None, solid)
+            lat.step(3)
+            f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+            lat.get_populations(f)
+            torch.cuda.synchronize()
+            out.append(f)
+    assert torch.isfinite(out[0]).all()
+    assert torch.equal(out[0], out[1])
