@@ -77,6 +77,7 @@ struct lb_ctx {
   void* psi = nullptr;     // [2][N] pseudopotential, arithmetic type
   uint8_t* mask = nullptr; // [N], allocated on first use
   bool has_solid = false;
+  bool tiled = false;  // the current population grid is in the tile-major layout (float64 only)
   double* partial = nullptr;
   double* result = nullptr;
   int* flag = nullptr;
@@ -223,9 +224,19 @@ bool staged_wide(const lb_ctx* ctx) { return ctx->p.storage == LB_F64 && ctx->p.
 
 template <int ST, bool SOLID, bool RECORD>
 void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
-                     typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
+                     typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec,
+                     bool tiled = false) {
   const uint8_t* m = SOLID ? ctx->mask : nullptr;
   if constexpr (ST == ST_F64) {
+    if constexpr (!SOLID && !RECORD) {
+      if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+        const FusedTiling t = ctx->tiling_wide;
+        k_fused_pair<ST, false, kWideTY, false, true, kWideTX, kModelSC, true>
+            <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                               nullptr);
+        return;
+      }
+    }
     if constexpr (!SOLID) {
       if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx)) {
         const FusedTiling t = ctx->tiling_wide;
@@ -292,7 +303,8 @@ void launch_cg_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
 
 template <int ST>
 lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
-                       typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec) {
+                       typename StorageTraits<ST>::store_t* fout, typename StorageTraits<ST>::real* rec,
+                       bool tiled = false) {
   if (ctx->model == LB_MODEL_COLOUR_GRADIENT) {
     // lb_set_model admits float64 and float32 storage without solids only
     if (ST == ST_F16S || ctx->has_solid || rec != nullptr) return LB_EINVAL;
@@ -305,18 +317,45 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
       else launch_fused_as<ST, true, false>(ctx, fin, fout, rec);
     } else {
       if (rec) launch_fused_as<ST, false, true>(ctx, fin, fout, rec);
-      else launch_fused_as<ST, false, false>(ctx, fin, fout, rec);
+      else launch_fused_as<ST, false, false>(ctx, fin, fout, rec, tiled);
     }
   });
+}
+
+// The staged float64 Shan-Chen step on 64 x 4 tiles runs on the tile-major
+// layout (one contiguous block per tile plane instead of 38 streams).
+bool tiled_ok(const lb_ctx* ctx) {
+  return ctx->p.storage == LB_F64 && !ctx->has_solid && ctx->model == LB_MODEL_SHAN_CHEN &&
+         ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx) && ctx->p.ny % kWideTY == 0 &&
+         2.0 * Q * ctx->g.nx * ctx->g.ny * 8.0 < 4294967296.0;
+}
+
+// Put the current grid in the tile-major (tiled) or the structure-of-arrays
+// layout, through the other grid.  Every entry point other than the step
+// asks for the structure-of-arrays layout before it touches the grid.
+lb_status set_layout(lb_ctx* ctx, bool tiled) {
+  if (ctx->tiled == tiled) return LB_OK;
+  k_relayout<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const double*>(ctx->grid[ctx->cur]),
+                                                              static_cast<double*>(ctx->grid[ctx->cur ^ 1]), ctx->g,
+                                                              tiled ? 1 : 0);
+  LB_HIP(hipGetLastError());
+  ctx->cur ^= 1;
+  ctx->tiled = tiled;
+  return LB_OK;
 }
 
 template <int ST>
 lb_status fused_step_impl(lb_ctx* ctx, int n) {
   using store = typename StorageTraits<ST>::store_t;
+  const bool tiled = tiled_ok(ctx);
+  {
+    lb_status st = set_layout(ctx, tiled);
+    if (st != LB_OK) return st;
+  }
   for (int s = 0; s < n; ++s) {
     const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
     store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
-    lb_status st = launch_fused<ST>(ctx, fin, fout, nullptr);
+    lb_status st = launch_fused<ST>(ctx, fin, fout, nullptr, tiled);
     if (st != LB_OK) return st;
     ctx->cur ^= 1;
   }
@@ -333,6 +372,10 @@ template <int ST>
 lb_status step_impl(lb_ctx* ctx, int n) {
   if (use_fused(ctx)) return fused_step_impl<ST>(ctx, n);
   if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // the colour-gradient step is fused only
+  {
+    lb_status st = set_layout(ctx, false);
+    if (st != LB_OK) return st;
+  }
   using store = typename StorageTraits<ST>::store_t;
   using real = typename StorageTraits<ST>::real;
   const int nb = blocks_for(ctx->g.N);
@@ -908,6 +951,7 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b, c
   lb_status st = by_storage(ctx, [&](auto tag) { return init_impl<decltype(tag)::value>(ctx, dra, drb, du); });
   if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
   release();
+  ctx->tiled = false;  // the initial state is written in the structure-of-arrays layout
   if (st == LB_OK) ctx->has_state = true;
   return st;
 }
@@ -926,6 +970,10 @@ lb_status lb_moments(lb_ctx* ctx, double* rho_a, double* rho_b, double* u, int o
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   const size_t N = static_cast<size_t>(ctx->g.N);
   if (on_device) {
     lb_status st = by_storage(ctx, [&](auto tag) { return moments_impl<decltype(tag)::value>(ctx, rho_a, rho_b, u); });
@@ -958,6 +1006,10 @@ lb_status lb_get_populations(lb_ctx* ctx, double* f, int on_device) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   const size_t N = static_cast<size_t>(ctx->g.N);
   if (!on_device) {
     lb_status st = ensure_plane(ctx);
@@ -980,6 +1032,10 @@ lb_status lb_set_populations(lb_ctx* ctx, const double* f, int on_device) {
   if (ctx == nullptr || f == nullptr) return LB_EINVAL;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   const size_t N = static_cast<size_t>(ctx->g.N);
   lb_status st = ensure_plane(ctx);
   if (st != LB_OK) return st;
@@ -1018,6 +1074,10 @@ lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   int blocks = blocks_for(ctx->g.N);
   if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
   lb_status st = by_storage(ctx, [&](auto tag) { return totals_impl<decltype(tag)::value>(ctx, blocks); });
@@ -1072,6 +1132,10 @@ lb_status lb_save_state(lb_ctx* ctx, void* dst, int on_device) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   LB_HIP(hipMemcpyAsync(dst, ctx->grid[ctx->cur], ctx->grid_bytes,
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
   LB_HIP(hipStreamSynchronize(ctx->stream));
@@ -1087,6 +1151,7 @@ lb_status lb_restore_state(lb_ctx* ctx, const void* src, int on_device) {
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
   LB_HIP(hipStreamSynchronize(ctx->stream));
   ctx->has_state = true;
+  ctx->tiled = false;  // snapshots are in the structure-of-arrays layout
   return LB_OK;
 }
 
@@ -1110,6 +1175,10 @@ lb_status lb_step_record(lb_ctx* ctx, void* record) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  {
+    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
+    if (lst != LB_OK) return lst;
+  }
   return by_storage(ctx, [&](auto tag) { return step_record_impl<decltype(tag)::value>(ctx, record); });
 }
 

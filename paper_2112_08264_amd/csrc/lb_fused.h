@@ -308,6 +308,41 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 }
 
 // ---------------------------------------------------------------------------
+// Tile-major layout of the float64 state (the staged Shan-Chen step on
+// 64 x 4 tiles, nx a multiple of 64 and ny of 4): population plane
+// ki = k Q + i of node (x, y, z) at
+//   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
+//   tile = (y / 4) (nx / 64) + x / 64,
+// so that one tile's 38 population rows of one plane are a single
+// contiguous 77,824-byte block, and a workgroup marching that tile's column
+// reads one stream instead of 38.  Offsets within a plane stay below 2^32
+// bytes when 38 nx ny 8 does.
+// ---------------------------------------------------------------------------
+constexpr int kTileX = 64, kTileY = 4, kTileNodes = kTileX * kTileY;
+
+__device__ __forceinline__ long long tile_major_index(int ki, int x, int y, int z, const Geometry& g) {
+  const long long tile = (long long)(y >> 2) * (g.nx >> 6) + (x >> 6);
+  return (long long)z * (2LL * Q * g.nx * g.ny) + (tile * (2 * Q) + ki) * kTileNodes + (y & 3) * kTileX + (x & 63);
+}
+
+// Float64 state between the structure-of-arrays layout (plane ki at
+// ki * Npad, node n = x + nx (y + ny z)) and the tile-major one; to_tiled
+// selects the direction.  One work-item per node, 38 values each.
+__global__ void __launch_bounds__(kBlock) k_relayout(const double* __restrict__ src, double* __restrict__ dst,
+                                                     Geometry g, int to_tiled) {
+  const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((long long)g.nx * g.ny));
+  const long long t = tile_major_index(0, x, y, z, g);
+#pragma unroll
+  for (int ki = 0; ki < 2 * Q; ++ki) {
+    const long long s = (long long)ki * g.Npad + n, d = t + (long long)ki * kTileNodes;
+    if (to_tiled) dst[d] = src[s];
+    else dst[s] = src[d];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Component-pair variant (float64 Shan-Chen; every colour-gradient step).
 // Each wave holds 32 nodes of one tile row for both components: lanes 0..31
 // carry component A, lanes 32..63 component B of the same nodes, and the
@@ -335,7 +370,11 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 // rows x TX nodes + 2 (TY + 2) side nodes) float64: 120,384 bytes for
 // 64 x 4 tiles, 103,360 for 32 x 8, so one workgroup per compute unit.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC>
+//
+// TILED: the populations are in the tile-major layout above (staged float64
+// Shan-Chen step on 64 x 4 tiles only); only the addressing differs.
+template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC,
+          bool TILED = false>
 __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                             store_t<ST>* __restrict__ fout,
                                                             const uint8_t* __restrict__ mask, Geometry g,
@@ -353,6 +392,8 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
   static_assert(MODEL == kModelSC || (!SOLID && !RECORD), "the colour-gradient step has no solids and no adjoint record");
+  static_assert(!TILED || (STAGED && TX == kTileX && TY == kTileY && MODEL == kModelSC && !SOLID && !RECORD),
+                "the tile-major layout serves the staged float64 Shan-Chen step on 64 x 4 tiles");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -409,18 +450,23 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   bool hrows = false;        // halo node in a stage row (else in a side column)
   if constexpr (STAGED) {
     auto wrapy = [&](int y) { return ((y % g.ny) + g.ny) % g.ny; };  // y may be off by more than ny when ny < TY
+    // element offset of node (x, y) within population plane 0 of a z-plane
+    auto in_plane = [&](int x, int y) -> uint32_t {
+      if constexpr (TILED) return (uint32_t)tile_major_index(0, x, y, 0, g);
+      else return (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
+    };
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int cq = 64 * q + lane;
       on16[q] = cq < RY * (TX / 2);
       const int r = cq / (TX / 2), xp = cq % (TX / 2);
-      voff16[q] = (uint32_t)(((uint32_t)(tx0 + 2 * xp) + (uint32_t)g.nx * (uint32_t)wrapy(ty0 + r - 1)) * 8u);
+      voff16[q] = in_plane(tx0 + 2 * xp, wrapy(ty0 + r - 1)) * 8u;  // x even: both nodes in one tile row
     }
     on4 = lane < 4 * RY;
     {
       const int sn = lane >> 1, r = sn % RY;
       const int sx = sn < RY ? (tx0 == 0 ? g.nx - 1 : tx0 - 1) : (tx0 + TX == g.nx ? 0 : tx0 + TX);
-      voff4 = (uint32_t)(((uint32_t)sx + (uint32_t)g.nx * (uint32_t)wrapy(ty0 + r - 1)) * 8u + 4u * (uint32_t)(lane & 1));
+      voff4 = in_plane(sx, wrapy(ty0 + r - 1)) * 8u + 4u * (uint32_t)(lane & 1);
     }
     ibase = (k * Q * RY + ly + 1) * TX + lx;
     hrows = hx >= 0 && hx < TX;
@@ -432,12 +478,14 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     typedef __attribute__((address_space(3))) void lds_void;
     typedef __attribute__((address_space(1))) void glb_void;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const char* zbase = reinterpret_cast<const char*>(fin) + (size_t)plane_n * (size_t)zz * 8u;
+    const size_t zstride = TILED ? (size_t)KI * (size_t)plane_n : (size_t)plane_n;  // elements per z-plane
+    const size_t kstride = TILED ? (size_t)kTileNodes : (size_t)g.Npad;              // ... per population plane
+    const char* zbase = reinterpret_cast<const char*>(fin) + zstride * (size_t)zz * 8u;
 #pragma unroll
     for (int m = 0; m < (KI + NW - 1) / NW; ++m) {
       const int ki = wv + NW * m;
       if (ki < KI) {
-        const char* base = zbase + (size_t)ki * (size_t)g.Npad * 8u;
+        const char* base = zbase + (size_t)ki * kstride * 8u;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
           if (on16[q])
@@ -467,6 +515,13 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     }
   };
 
+  auto rho_tiled = [&](int x, int y, int z, int kk, real (&v)[Q]) -> real {
+    const long long t = tile_major_index(kk * Q, x, y, z, g);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = decode<ST>(fin[t + (long long)i * kTileNodes], c.shift[kk][i]);
+    return density<real>(v);
+  };
+
   // ring slot s <- plane z; interior lanes keep their populations in `keep`
   auto fill = [&](int s, int z, real (&keep)[Q]) {
     const long long zoff = plane_n * z;
@@ -474,7 +529,8 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       const long long n = row + zoff;
       bool solid = false;
       if constexpr (SOLID) solid = mask[n] != 0;
-      ring_put(s, k, ly + 1, lx + 1, rho_of(n, kplane, k, keep), solid, 32);
+      const real rho = TILED ? rho_tiled(gx, gy, z, k, keep) : rho_of(n, kplane, k, keep);
+      ring_put(s, k, ly + 1, lx + 1, rho, solid, 32);
       if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid;
     }
     if (has_halo) {
@@ -482,7 +538,8 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       bool solid = false;
       if constexpr (SOLID) solid = mask[n] != 0;
       real tmp[Q];
-      ring_put(s, hk, hy + 1, hx + 1, rho_of(n, hkplane, hk, tmp), solid, 1);
+      const real rho = TILED ? rho_tiled(hgx, hgy, z, hk, tmp) : rho_of(n, hkplane, hk, tmp);
+      ring_put(s, hk, hy + 1, hx + 1, rho, solid, 1);
       if constexpr (SOLID) if (hk == 0) ring_solid[s][hy + 1][hx + 1] = solid;
     }
   };
@@ -573,8 +630,13 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       const long long here = row + plane_n * z;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        long long dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
-                        (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
+        long long dst;
+        if constexpr (TILED) {
+          dst = tile_major_index(k * Q + i, X[CX[i] + 1], Y[CY[i] + 1], Z[CZ[i] + 1], g);
+        } else {
+          dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
+                (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
+        }
         if constexpr (SOLID)
           if ((bb >> i) & 1u) dst = kplane + (long long)OPP[i] * g.Npad + here;
         fout[dst] = encode<ST>(fs[i], c.shift[k][i]);
