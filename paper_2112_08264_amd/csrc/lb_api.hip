@@ -276,8 +276,15 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
 // float storages' tiling).
 template <int ST>
 void launch_cg_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
-                  typename StorageTraits<ST>::store_t* fout) {
+                  typename StorageTraits<ST>::store_t* fout, bool tiled = false) {
   if constexpr (ST == ST_F64) {
+    if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+      const FusedTiling t = ctx->tiling_wide;
+      k_fused_pair<ST, false, kWideTY, false, true, kWideTX, kModelCG, true>
+          <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                             nullptr);
+      return;
+    }
     if (ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx)) {
       const FusedTiling t = ctx->tiling_wide;
       k_fused_pair<ST, false, kWideTY, false, true, kWideTX, kModelCG>
@@ -308,7 +315,7 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
   if (ctx->model == LB_MODEL_COLOUR_GRADIENT) {
     // lb_set_model admits float64 and float32 storage without solids only
     if (ST == ST_F16S || ctx->has_solid || rec != nullptr) return LB_EINVAL;
-    return launch(ctx, SLOT_FUSED, [&] { launch_cg_as<ST>(ctx, fin, fout); });
+    return launch(ctx, SLOT_FUSED, [&] { launch_cg_as<ST>(ctx, fin, fout, tiled); });
   }
   const bool solid = ctx->has_solid;
   return launch(ctx, SLOT_FUSED, [&] {
@@ -322,12 +329,12 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
   });
 }
 
-// The staged float64 Shan-Chen step on 64 x 4 tiles runs on the tile-major
-// layout (one contiguous block per tile plane instead of 38 streams).
+// The staged float64 step on 64 x 4 tiles (either model) runs on the
+// tile-major layout (one contiguous block per tile plane instead of 38
+// streams).
 bool tiled_ok(const lb_ctx* ctx) {
-  return ctx->p.storage == LB_F64 && !ctx->has_solid && ctx->model == LB_MODEL_SHAN_CHEN &&
-         ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx) && ctx->p.ny % kWideTY == 0 &&
-         2.0 * Q * ctx->g.nx * ctx->g.ny * 8.0 < 4294967296.0;
+  return ctx->p.storage == LB_F64 && !ctx->has_solid && ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx) &&
+         ctx->p.ny % kWideTY == 0 && 2.0 * Q * ctx->g.nx * ctx->g.ny * 8.0 < 4294967296.0;
 }
 
 // Put the current grid in the tile-major (tiled) or the structure-of-arrays

@@ -308,8 +308,8 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 }
 
 // ---------------------------------------------------------------------------
-// Tile-major layout of the float64 state (the staged Shan-Chen step on
-// 64 x 4 tiles, nx a multiple of 64 and ny of 4): population plane
+// Tile-major layout of the float64 state (the staged step on 64 x 4 tiles,
+// nx a multiple of 64 and ny of 4): population plane
 // ki = k Q + i of node (x, y, z) at
 //   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
 //   tile = (y / 4) (nx / 64) + x / 64,
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(kBlock) k_relayout(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 //
 // TILED: the populations are in the tile-major layout above (staged float64
-// Shan-Chen step on 64 x 4 tiles only); only the addressing differs.
+// step on 64 x 4 tiles, either model); only the addressing differs.
 template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC,
           bool TILED = false>
 __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
@@ -392,8 +392,8 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
   static_assert(MODEL == kModelSC || (!SOLID && !RECORD), "the colour-gradient step has no solids and no adjoint record");
-  static_assert(!TILED || (STAGED && TX == kTileX && TY == kTileY && MODEL == kModelSC && !SOLID && !RECORD),
-                "the tile-major layout serves the staged float64 Shan-Chen step on 64 x 4 tiles");
+  static_assert(!TILED || (STAGED && TX == kTileX && TY == kTileY && !SOLID && !RECORD),
+                "the tile-major layout serves the staged float64 step on 64 x 4 tiles");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];

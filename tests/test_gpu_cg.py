@@ -56,11 +56,12 @@ def run_gpu(shape, p, r1, r2, steps, u=None, storage="f64", kernel="auto"):
         return f.cpu().numpy().reshape((2, 19) + tuple(shape))
 
 
-# (9, 17, 64): staged 64 x 4 tiles; (8, 12, 32): staged 32 x 8; the others
-# unstaged, with ragged tiles; (64, 64, 64) splits z into chunks of 4 planes
+# (9, 17, 64): staged 64 x 4 tiles; (5, 8, 64) and (3, 12, 128): the same on the
+# tile-major layout (ny a multiple of 4); (8, 12, 32): staged 32 x 8; the others
+# unstaged, with ragged tiles
 @pytest.mark.parametrize("kernel", ["fused", "fused_staged"])
-@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 7), (3, 1, 9), (1, 1, 1), (9, 17, 64), (8, 12, 32),
-                                   (2, 9, 300)])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 7), (3, 1, 9), (1, 1, 1), (9, 17, 64), (5, 8, 64), (3, 12, 128),
+                                   (8, 12, 32), (2, 9, 300)])
 def test_f64_colour_gradient_bitwise_equal_to_oracle(shape, kernel):
     _say(f"case cg f64 bitwise shape={shape} kernel={kernel}")
     r1, r2, u = _mixed(shape, 41)
