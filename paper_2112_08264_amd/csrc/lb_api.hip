@@ -255,6 +255,22 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
     k_fused_pair<ST, SOLID, kFusedTY, RECORD, false>
         <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   } else {
+    if constexpr (!SOLID) {
+      if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+        if (ST == ST_F32 && ctx->tall) {
+          const FusedTiling t = ctx->tiling_tall;
+          k_fused<ST, false, kFloatTallTY, kFloatDepth, RECORD, kFloatTX, true>
+              <<<dim3(t.total), dim3(128 * kFloatTallTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g,
+                                                                                             ctx->c, t, rec);
+        } else {
+          const FusedTiling t = ctx->tiling;
+          k_fused<ST, false, kFloatTY, kFloatDepth, RECORD, kFloatTX, true>
+              <<<dim3(t.total), dim3(128 * kFloatTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g,
+                                                                                         ctx->c, t, rec);
+        }
+        return;
+      }
+    }
     if constexpr (ST == ST_F32 && !SOLID) {
       if (ctx->tall) {
         const FusedTiling t = ctx->tiling_tall;
@@ -323,7 +339,7 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
       if (rec) launch_fused_as<ST, true, true>(ctx, fin, fout, rec);
       else launch_fused_as<ST, true, false>(ctx, fin, fout, rec);
     } else {
-      if (rec) launch_fused_as<ST, false, true>(ctx, fin, fout, rec);
+      if (rec) launch_fused_as<ST, false, true>(ctx, fin, fout, rec, tiled);
       else launch_fused_as<ST, false, false>(ctx, fin, fout, rec, tiled);
     }
   });
@@ -333,19 +349,34 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
 // tile-major layout (one contiguous block per tile plane instead of 38
 // streams).
 bool tiled_ok(const lb_ctx* ctx) {
-  return ctx->p.storage == LB_F64 && !ctx->has_solid && ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx) &&
-         ctx->p.ny % kWideTY == 0 && 2.0 * Q * ctx->g.nx * ctx->g.ny * 8.0 < 4294967296.0;
+  if (ctx->has_solid || ctx->p.nx % kTileX != 0 || ctx->p.ny % kTileY != 0 ||
+      2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem >= 4294967296.0)
+    return false;
+  if (ctx->p.storage == LB_F64) return ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx);
+  return ctx->model == LB_MODEL_SHAN_CHEN;  // float storage: k_fused (the colour-gradient kernel keeps the SoA)
 }
 
 // Put the current grid in the tile-major (tiled) or the structure-of-arrays
 // layout, through the other grid.  Every entry point other than the step
 // asks for the structure-of-arrays layout before it touches the grid.
+template <typename F>
+lb_status by_storage(const lb_ctx* ctx, F&& f);
+
+// Copy the grid at src into dst, from the tile-major layout (to_tiled = 0)
+// or into it (1).
+lb_status relayout(lb_ctx* ctx, const void* src, void* dst, int to_tiled) {
+  return by_storage(ctx, [&](auto tag) {
+    using store = typename StorageTraits<decltype(tag)::value>::store_t;
+    k_relayout<store><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const store*>(src),
+                                                                        static_cast<store*>(dst), ctx->g, to_tiled);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+}
+
 lb_status set_layout(lb_ctx* ctx, bool tiled) {
   if (ctx->tiled == tiled) return LB_OK;
-  k_relayout<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(static_cast<const double*>(ctx->grid[ctx->cur]),
-                                                              static_cast<double*>(ctx->grid[ctx->cur ^ 1]), ctx->g,
-                                                              tiled ? 1 : 0);
-  LB_HIP(hipGetLastError());
+  lb_status st = relayout(ctx, ctx->grid[ctx->cur], ctx->grid[ctx->cur ^ 1], tiled ? 1 : 0);
+  if (st != LB_OK) return st;
   ctx->cur ^= 1;
   ctx->tiled = tiled;
   return LB_OK;
@@ -580,8 +611,17 @@ lb_status step_record_impl(lb_ctx* ctx, void* record) {
   real* rec = static_cast<real*>(record);
   lb_status st;
   if (use_fused(ctx)) {
-    st = launch_fused<ST>(ctx, fin, fout, rec);
+    // the float kernel records on the tile-major layout too (the record is
+    // indexed by node); the float64 record step runs on the structure of arrays
+    const bool tiled = ST != ST_F64 && tiled_ok(ctx);
+    st = set_layout(ctx, tiled);
+    if (st != LB_OK) return st;
+    fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+    fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+    st = launch_fused<ST>(ctx, fin, fout, rec, tiled);
   } else {
+    st = set_layout(ctx, false);
+    if (st != LB_OK) return st;
     st = launch(ctx, SLOT_ADJ_MOMENTS, [&] {
       k_adj_moments<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(fin, mask_or_null(ctx), rec, ctx->g, ctx->c);
     });
@@ -1139,6 +1179,12 @@ lb_status lb_save_state(lb_ctx* ctx, void* dst, int on_device) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
+  if (on_device && ctx->tiled) {  // the snapshot in the structure-of-arrays layout; the state stays as it is
+    lb_status st = relayout(ctx, ctx->grid[ctx->cur], dst, 0);
+    if (st != LB_OK) return st;
+    LB_HIP(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+  }
   {
     lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
     if (lst != LB_OK) return lst;
@@ -1182,10 +1228,6 @@ lb_status lb_step_record(lb_ctx* ctx, void* record) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  {
-    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
-    if (lst != LB_OK) return lst;
-  }
   return by_storage(ctx, [&](auto tag) { return step_record_impl<decltype(tag)::value>(ctx, record); });
 }
 

@@ -80,6 +80,42 @@ __device__ __forceinline__ int fused_work_item(int b, int total, int per_round) 
   return base + j * q + (j < r ? j : r) + s;
 }
 
+// ---------------------------------------------------------------------------
+// Tile-major population layout (fused steps without solids, nx a multiple
+// of 64 and ny of 4): population plane ki = k Q + i of node (x, y, z) at
+// element
+//   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
+//   tile = (y / 4) (nx / 64) + x / 64,
+// so that one 64 x 4 tile's 38 population rows of one plane are a single
+// contiguous block (77,824 bytes in float64), and a workgroup marching that
+// tile's column reads one stream instead of 38.  Offsets within a plane stay
+// below 2^32 bytes when 38 nx ny times the element size does.
+// ---------------------------------------------------------------------------
+constexpr int kTileX = 64, kTileY = 4, kTileNodes = kTileX * kTileY;
+
+__device__ __forceinline__ long long tile_major_index(int ki, int x, int y, int z, const Geometry& g) {
+  const long long tile = (long long)(y >> 2) * (g.nx >> 6) + (x >> 6);
+  return (long long)z * (2LL * Q * g.nx * g.ny) + (tile * (2 * Q) + ki) * kTileNodes + (y & 3) * kTileX + (x & 63);
+}
+
+// State between the structure-of-arrays layout (plane ki at ki * Npad, node
+// n = x + nx (y + ny z)) and the tile-major one; to_tiled selects the
+// direction.  One work-item per node, 38 values each.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_relayout(const T* __restrict__ src, T* __restrict__ dst, Geometry g,
+                                                     int to_tiled) {
+  const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((long long)g.nx * g.ny));
+  const long long t = tile_major_index(0, x, y, z, g);
+#pragma unroll
+  for (int ki = 0; ki < 2 * Q; ++ki) {
+    const long long s = (long long)ki * g.Npad + n, d = t + (long long)ki * kTileNodes;
+    if (to_tiled) dst[d] = src[s];
+    else dst[s] = src[d];
+  }
+}
+
 // RECORD: also write the moment record of the pre-collision state (rho_A,
 // rho_B, m_A, m_B, psi_A, psi_B as [10][N], zero at solid nodes) that the
 // adjoint step consumes.
@@ -87,7 +123,10 @@ __device__ __forceinline__ int fused_work_item(int b, int total, int per_round) 
 // TX = 32: each wave carries two rows of 32 nodes; TX = 64: one row of 64
 // (whole 128-byte lines of float16 rows, fewer partly written lines at the
 // tile's x edges).  A workgroup has 2 TY / (64 / TX) waves.
-template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX>
+//
+// TILED: the populations are in the tile-major layout (no solids, TX = 64);
+// only the addressing differs.
+template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX, bool TILED = false>
 __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>* __restrict__ fin,
                                                               store_t<ST>* __restrict__ fout,
                                                               const uint8_t* __restrict__ mask, Geometry g,
@@ -105,6 +144,7 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   static_assert(TX == 32 || TX == 64, "a wave covers two rows of 32 or one row of 64");
   static_assert(TY % RPW == 0 && TY / RPW >= 3, "three waves per component carry the halo");
   static_assert(2 * TY + (CORNERS_IN_ROWS ? 0 : 4) <= 64, "one wave carries the side columns");
+  static_assert(!TILED || (!SOLID && TX == kTileX && TY % kTileY == 0), "the tile-major layout has no solids");
   __shared__ real ring[NS][2][RY][RX];
   __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
   __shared__ uint8_t ring_solid[SOLID ? NS : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -167,6 +207,19 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
     for (int i = 0; i < Q; ++i)
       v[i] = decode<ST>(*reinterpret_cast<const store*>(fk + (size_t)i * pbytes + b), c.shift[k][i]);
   };
+  // TILED: the same from the in-plane byte offset tb of population plane 0
+  // (tile-major) and the plane index z.  The base of each population row
+  // block is wave-uniform (scalar registers), as in load19.
+  const size_t zbytes = (size_t)(2 * Q) * (size_t)plane_n * ES;
+  constexpr size_t kRowBlock = (size_t)kTileNodes * ES;  // bytes of one population's tile rows
+  const uint32_t row_t = TILED ? (uint32_t)tile_major_index(0, gx, gy, 0, g) * ES : 0u;
+  const uint32_t hrow_t = TILED ? (uint32_t)tile_major_index(0, hgx, hgy, 0, g) * ES : 0u;
+  auto load19t = [&](uint32_t tb, int z, real (&v)[Q]) {
+    const char* zb = reinterpret_cast<const char*>(fin) + (size_t)z * zbytes + (size_t)(k * Q) * kRowBlock;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      v[i] = decode<ST>(*reinterpret_cast<const store*>(zb + (size_t)i * kRowBlock + tb), c.shift[k][i]);
+  };
   auto psi_from = [&](const real (&v)[Q], bool solid) -> real {
     if (SOLID && solid) return real(0);
     return pseudopotential(density<real>(v), coef_ref<real>(c));
@@ -195,16 +248,26 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   real hold[D][Q], pre[Q], hpre[Q];  // hold[d]: populations of plane z + d
   // prologue: psi of planes z0 - 1 .. z0 + D - 1, populations of z0 .. z0 + D - 1
   {
-    const uint32_t zo = plane_n * (uint32_t)wrapz(z0 - 1);
-    load19(row + zo, pre);
-    if (has_halo) load19(hrow + zo, hpre);
+    if constexpr (TILED) {
+      load19t(row_t, wrapz(z0 - 1), pre);
+      if (has_halo) load19t(hrow_t, wrapz(z0 - 1), hpre);
+    } else {
+      const uint32_t zo = plane_n * (uint32_t)wrapz(z0 - 1);
+      load19(row + zo, pre);
+      if (has_halo) load19(hrow + zo, hpre);
+    }
     publish(z0 - 1, pre, hpre);
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const uint32_t zo = plane_n * (uint32_t)wrapz(z0 + d);
-    load19(row + zo, hold[d]);
-    if (has_halo) load19(hrow + zo, hpre);
+    if constexpr (TILED) {
+      load19t(row_t, wrapz(z0 + d), hold[d]);
+      if (has_halo) load19t(hrow_t, wrapz(z0 + d), hpre);
+    } else {
+      const uint32_t zo = plane_n * (uint32_t)wrapz(z0 + d);
+      load19(row + zo, hold[d]);
+      if (has_halo) load19(hrow + zo, hpre);
+    }
     publish(z0 + d, hold[d], hpre);
   }
   __syncthreads();
@@ -215,15 +278,29 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
   const uint32_t X[3] = {(uint32_t)xm, (uint32_t)gx, (uint32_t)xp};
   const uint32_t Y[3] = {(uint32_t)g.nx * ym, (uint32_t)g.nx * gy, (uint32_t)g.nx * yp};
+  // TILED: in-plane byte offsets of the nine (x +- 1, y +- 1) destinations
+  uint32_t T9[3][3] = {};
+  if constexpr (TILED) {
+    const int xs3[3] = {xm, gx, xp}, ys3[3] = {ym, gy, yp};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) T9[b][a] = (uint32_t)tile_major_index(0, xs3[a], ys3[b], 0, g) * ES;
+  }
 
   for (int j = 0; j < zlen; ++j) {
     const int z = z0 + j;
     const bool more = j + D <= zlen;  // psi of plane z + D is needed by a later collision
     // ---- A: issue the loads of plane z + D ----
     if (more) {
-      const uint32_t zo = plane_n * (uint32_t)wrapz(z + D);
-      load19(row + zo, pre);
-      if (has_halo) load19(hrow + zo, hpre);
+      if constexpr (TILED) {
+        load19t(row_t, wrapz(z + D), pre);
+        if (has_halo) load19t(hrow_t, wrapz(z + D), hpre);
+      } else {
+        const uint32_t zo = plane_n * (uint32_t)wrapz(z + D);
+        load19(row + zo, pre);
+        if (has_halo) load19(hrow + zo, hpre);
+      }
     }
     __asm__ volatile("" ::: "memory");
 
@@ -291,7 +368,13 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
             }
           }
         }
-        *reinterpret_cast<store*>(ok + (size_t)di * pbytes + dn * ES) = encode<ST>(fs, c.shift[k][i]);
+        if constexpr (TILED) {
+          const int zz = CZ[i] < 0 ? wrapz(z - 1) : (CZ[i] > 0 ? wrapz(z + 1) : z);
+          char* zb = reinterpret_cast<char*>(fout) + (size_t)zz * zbytes + (size_t)(k * Q + i) * kRowBlock;
+          *reinterpret_cast<store*>(zb + T9[CY[i] + 1][CX[i] + 1]) = encode<ST>(fs, c.shift[k][i]);
+        } else {
+          *reinterpret_cast<store*>(ok + (size_t)di * pbytes + dn * ES) = encode<ST>(fs, c.shift[k][i]);
+        }
       }
     }
 
@@ -304,41 +387,6 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
       for (int d = 0; d + 1 < D; ++d) hold[d][i] = hold[d + 1][i];
       hold[D - 1][i] = pre[i];
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Tile-major layout of the float64 state (the staged step on 64 x 4 tiles,
-// nx a multiple of 64 and ny of 4): population plane
-// ki = k Q + i of node (x, y, z) at
-//   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
-//   tile = (y / 4) (nx / 64) + x / 64,
-// so that one tile's 38 population rows of one plane are a single
-// contiguous 77,824-byte block, and a workgroup marching that tile's column
-// reads one stream instead of 38.  Offsets within a plane stay below 2^32
-// bytes when 38 nx ny 8 does.
-// ---------------------------------------------------------------------------
-constexpr int kTileX = 64, kTileY = 4, kTileNodes = kTileX * kTileY;
-
-__device__ __forceinline__ long long tile_major_index(int ki, int x, int y, int z, const Geometry& g) {
-  const long long tile = (long long)(y >> 2) * (g.nx >> 6) + (x >> 6);
-  return (long long)z * (2LL * Q * g.nx * g.ny) + (tile * (2 * Q) + ki) * kTileNodes + (y & 3) * kTileX + (x & 63);
-}
-
-// Float64 state between the structure-of-arrays layout (plane ki at
-// ki * Npad, node n = x + nx (y + ny z)) and the tile-major one; to_tiled
-// selects the direction.  One work-item per node, 38 values each.
-__global__ void __launch_bounds__(kBlock) k_relayout(const double* __restrict__ src, double* __restrict__ dst,
-                                                     Geometry g, int to_tiled) {
-  const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (n >= g.N) return;
-  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((long long)g.nx * g.ny));
-  const long long t = tile_major_index(0, x, y, z, g);
-#pragma unroll
-  for (int ki = 0; ki < 2 * Q; ++ki) {
-    const long long s = (long long)ki * g.Npad + n, d = t + (long long)ki * kTileNodes;
-    if (to_tiled) dst[d] = src[s];
-    else dst[s] = src[d];
   }
 }
 

@@ -200,20 +200,22 @@ def test_recompute_reproduces_forward_states_bitwise():
         assert torch.equal(f_ref, f_new)
 
 
+# (5, 8, 64) without solids: the float record step and the steps of the
+# snapshot path run on the tile-major layout, snapshots are written from it
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_record_path_equals_snapshot_path(storage):
+@pytest.mark.parametrize("shape,with_solid", [((7, 9, 40), True), ((5, 8, 64), False)])
+def test_record_path_equals_snapshot_path(storage, shape, with_solid):
     torch = _torch()
-    shape = (7, 9, 40)
     n = int(np.prod(shape))
     steps = 6
-    solid = synth.solid_mask(shape, np.array([[20.0, 4.0, 3.0]]), 2.2)
+    solid = synth.solid_mask(shape, np.array([[20.0, 4.0, 3.0]]), 2.2) if with_solid else None
     a, b = synth.fluid_fields(shape, 0.02, 45)
     g0 = np.random.default_rng(46).standard_normal(shape)
-    _say(f"case record vs snapshot adjoint {storage}")
+    _say(f"case record vs snapshot adjoint {storage} shape={shape} solid={with_solid}")
     results = []
     for use_record in (False, True):
         with P.Lattice(shape, tau=(0.9, 1.1), G=3.5, storage=storage) as lat:
-            lat.set_fields(a.ravel().copy(), b.ravel().copy(), None, solid.ravel().copy())
+            lat.set_fields(a.ravel().copy(), b.ravel().copy(), None, None if solid is None else solid.ravel().copy())
             nb, rb = P.lb_state_bytes(lat.ctx), P.lb_record_bytes(lat.ctx)
             snaps, recs = [], []
             for t in range(steps):
