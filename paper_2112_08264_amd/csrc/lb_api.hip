@@ -318,6 +318,12 @@ void launch_cg_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin,
         <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr);
   } else if constexpr (ST == ST_F32) {
     const FusedTiling t = ctx->tiling_cg;
+    if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+      k_fused_pair<ST, false, kFloatTY, false, false, kFloatTX, kModelCG, true>
+          <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                               nullptr);
+      return;
+    }
     k_fused_pair<ST, false, kFloatTY, false, false, kFloatTX, kModelCG>
         <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
                                                                              nullptr);
@@ -353,7 +359,7 @@ bool tiled_ok(const lb_ctx* ctx) {
       2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem >= 4294967296.0)
     return false;
   if (ctx->p.storage == LB_F64) return ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx);
-  return ctx->model == LB_MODEL_SHAN_CHEN;  // float storage: k_fused (the colour-gradient kernel keeps the SoA)
+  return true;  // float storage: k_fused (Shan-Chen) or the unstaged pair kernel (colour gradient)
 }
 
 // Put the current grid in the tile-major (tiled) or the structure-of-arrays

@@ -115,7 +115,9 @@ def test_colour_gradient_moments_and_totals():
         assert abs(N1 - M1) <= 1e-13 * M1 and abs(N2 - M2) <= 1e-13 * M2
 
 
-def test_f32_one_step_from_an_oracle_state():
+# (24, 24, 32): structure of arrays; (6, 12, 64): the tile-major layout
+@pytest.mark.parametrize("shape", [(24, 24, 32), (6, 12, 64)])
+def test_f32_one_step_from_an_oracle_state(shape):
     """One float32 step from a state the float64 oracle has demixed for 40 steps
     (loaded by lb_set_populations, one rounding to float32): every population
     within 2e-6 of the oracle's next step.  Bound: float32 rounds each value to
@@ -123,7 +125,6 @@ def test_f32_one_step_from_an_oracle_state():
     plus the rounding of the loaded state, and the interface terms of nodes
     near |grad Theta| = 0 carry the same relative error."""
     torch = _torch()
-    shape = (24, 24, 32)
     n = int(np.prod(shape))
     _say(f"case cg f32 one step shape={shape}")
     f = CG.step(CG.init_equilibrium(*synth.colour_fields(shape, 44)), PAR, n=40)
