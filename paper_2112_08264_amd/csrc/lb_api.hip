@@ -255,6 +255,15 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
     k_fused_pair<ST, SOLID, kFusedTY, RECORD, false>
         <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t, rec);
   } else {
+    if constexpr (SOLID) {
+      if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+        const FusedTiling t = ctx->tiling;
+        k_fused<ST, true, kFloatTY, kFloatDepth, RECORD, kFloatTX, true>
+            <<<dim3(t.total), dim3(128 * kFloatTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, m, ctx->g, ctx->c, t,
+                                                                                       rec);
+        return;
+      }
+    }
     if constexpr (!SOLID) {
       if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
         if (ST == ST_F32 && ctx->tall) {
@@ -342,8 +351,8 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
   const bool solid = ctx->has_solid;
   return launch(ctx, SLOT_FUSED, [&] {
     if (solid) {
-      if (rec) launch_fused_as<ST, true, true>(ctx, fin, fout, rec);
-      else launch_fused_as<ST, true, false>(ctx, fin, fout, rec);
+      if (rec) launch_fused_as<ST, true, true>(ctx, fin, fout, rec, tiled);
+      else launch_fused_as<ST, true, false>(ctx, fin, fout, rec, tiled);
     } else {
       if (rec) launch_fused_as<ST, false, true>(ctx, fin, fout, rec, tiled);
       else launch_fused_as<ST, false, false>(ctx, fin, fout, rec, tiled);
@@ -355,11 +364,11 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
 // tile-major layout (one contiguous block per tile plane instead of 38
 // streams).
 bool tiled_ok(const lb_ctx* ctx) {
-  if (ctx->has_solid || ctx->p.nx % kTileX != 0 || ctx->p.ny % kTileY != 0 ||
-      2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem >= 4294967296.0)
+  if (ctx->p.nx % kTileX != 0 || ctx->p.ny % kTileY != 0 || 2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem >= 4294967296.0)
     return false;
-  if (ctx->p.storage == LB_F64) return ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx);
-  return true;  // float storage: k_fused (Shan-Chen) or the unstaged pair kernel (colour gradient)
+  if (ctx->p.storage == LB_F64)  // the staged pair kernel; lattices with solids run the unstaged one
+    return !ctx->has_solid && ctx->kernel == LB_KERNEL_FUSED_STAGED && staged_wide(ctx);
+  return true;  // float storage: k_fused (Shan-Chen, with or without solids) or the pair kernel (colour gradient)
 }
 
 // Put the current grid in the tile-major (tiled) or the structure-of-arrays

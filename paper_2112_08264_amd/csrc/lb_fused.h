@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(kBlock) k_relayout(const T* __restrict__ src, 
 // (whole 128-byte lines of float16 rows, fewer partly written lines at the
 // tile's x edges).  A workgroup has 2 TY / (64 / TX) waves.
 //
-// TILED: the populations are in the tile-major layout (no solids, TX = 64);
-// only the addressing differs.
+// TILED: the populations are in the tile-major layout (TX = 64); only the
+// addressing differs.
 template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX, bool TILED = false>
 __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>* __restrict__ fin,
                                                               store_t<ST>* __restrict__ fout,
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   static_assert(TX == 32 || TX == 64, "a wave covers two rows of 32 or one row of 64");
   static_assert(TY % RPW == 0 && TY / RPW >= 3, "three waves per component carry the halo");
   static_assert(2 * TY + (CORNERS_IN_ROWS ? 0 : 4) <= 64, "one wave carries the side columns");
-  static_assert(!TILED || (!SOLID && TX == kTileX && TY % kTileY == 0), "the tile-major layout has no solids");
+  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0), "tile-major rows are 64 nodes, tiles 4 rows");
   __shared__ real ring[NS][2][RY][RX];
   __shared__ real xch[NX][2][4][TY][TX];  // [plane slot][component][rho, mx, my, mz][y][x]
   __shared__ uint8_t ring_solid[SOLID ? NS : 1][SOLID ? RY : 1][SOLID ? RX : 1];
@@ -369,9 +369,11 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
           }
         }
         if constexpr (TILED) {
-          const int zz = CZ[i] < 0 ? wrapz(z - 1) : (CZ[i] > 0 ? wrapz(z + 1) : z);
-          char* zb = reinterpret_cast<char*>(fout) + (size_t)zz * zbytes + (size_t)(k * Q + i) * kRowBlock;
-          *reinterpret_cast<store*>(zb + T9[CY[i] + 1][CX[i] + 1]) = encode<ST>(fs, c.shift[k][i]);
+          // bounce-back (di != i) lands in this node's own slot di
+          const bool own = SOLID && di != i;
+          const int zz = own ? z : (CZ[i] < 0 ? wrapz(z - 1) : (CZ[i] > 0 ? wrapz(z + 1) : z));
+          char* zb = reinterpret_cast<char*>(fout) + (size_t)zz * zbytes + (size_t)(k * Q + di) * kRowBlock;
+          *reinterpret_cast<store*>(zb + (own ? T9[1][1] : T9[CY[i] + 1][CX[i] + 1])) = encode<ST>(fs, c.shift[k][i]);
         } else {
           *reinterpret_cast<store*>(ok + (size_t)di * pbytes + dn * ES) = encode<ST>(fs, c.shift[k][i]);
         }

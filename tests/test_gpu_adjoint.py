@@ -200,10 +200,11 @@ def test_recompute_reproduces_forward_states_bitwise():
         assert torch.equal(f_ref, f_new)
 
 
-# (5, 8, 64) without solids: the float record step and the steps of the
-# snapshot path run on the tile-major layout, snapshots are written from it
+# (5, 8, 64): the float record step and the steps of the snapshot path run on
+# the tile-major layout (with and without a solid sphere), snapshots are
+# written from it
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("shape,with_solid", [((7, 9, 40), True), ((5, 8, 64), False)])
+@pytest.mark.parametrize("shape,with_solid", [((7, 9, 40), True), ((5, 8, 64), False), ((5, 8, 64), True)])
 def test_record_path_equals_snapshot_path(storage, shape, with_solid):
     torch = _torch()
     n = int(np.prod(shape))
