@@ -37,12 +37,13 @@ constexpr int kFusedTY = 8;   // float64 fused tiles: 32 x 8 nodes, one row per 
 // fewer lines are written in part at the tile's x edges.
 constexpr int kFloatTX = 64;
 constexpr int kFloatTY = 4;
-// float32 storage without solids: 64 x 8 tiles, 16 waves at four per SIMD
-// (128 registers), measured 5.7% faster at 256^3 -- where their columns are
-// marched in chunks of at least 64 planes.  On 128^3 they take 16-plane
-// chunks and the step ran 7% slower, so such lattices keep 64 x 4, as do
-// float16-shifted storage (11% slower at 256^3), the colour-gradient kernel
-// (16%) and lattices with solids (3% at 512^3).
+// Float storage without solids: 64 x 8 tiles, 16 waves at four per SIMD
+// (128 registers), where their columns are marched in chunks of at least 64
+// planes.  At 256^3 on the tile-major layout: float32 1.30 -> 1.12 ms with
+// the layout change included (5.7% from the tiles alone in the structure of
+// arrays), float16-shifted 0.84 -> 0.75 ms (in the structure of arrays they
+// were 11% slower).  On 128^3 they would take 16-plane chunks (7% slower), so
+// such lattices keep 64 x 4, as do lattices with solids (3% slower at 512^3).
 constexpr int kFloatTallTY = 8;
 constexpr int kFloatTallMinChunk = 64;
 // Register prefetch depth of the float kernel: two planes ahead measured 2%
@@ -103,7 +104,7 @@ struct lb_ctx {
   FusedTiling tiling{};       // the storage's default fused kernel
   FusedTiling tiling_wide{};  // staged float64 kernel on 64 x 4 tiles (nx a multiple of 64)
   FusedTiling tiling_cg{};    // float32 colour-gradient kernel (64 x 4 tiles)
-  FusedTiling tiling_tall{};  // float32 Shan-Chen kernel without solids (64 x 8 tiles)
+  FusedTiling tiling_tall{};  // float Shan-Chen kernel without solids (64 x 8 tiles)
   bool tall = false;          // tiling_tall is used (its chunks hold >= kFloatTallMinChunk planes)
   int64_t bytes = 0;
 };
@@ -266,7 +267,7 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
     }
     if constexpr (!SOLID) {
       if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
-        if (ST == ST_F32 && ctx->tall) {
+        if (ctx->tall) {
           const FusedTiling t = ctx->tiling_tall;
           k_fused<ST, false, kFloatTallTY, kFloatDepth, RECORD, kFloatTX, true>
               <<<dim3(t.total), dim3(128 * kFloatTallTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g,
@@ -881,7 +882,7 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
     bool ok = make_tiling(p, f64 ? kFusedTX : kFloatTX, f64 ? kFusedTY : kFloatTY, cus, &ctx->tiling);
     if (ok && f64 && p.nx % kWideTX == 0) ok = make_tiling(p, kWideTX, kWideTY, cus, &ctx->tiling_wide);
     if (ok && !f64) ok = make_tiling(p, kFloatTX, kFloatTY, cus, &ctx->tiling_cg, true);
-    if (ok && p.storage == LB_F32) {
+    if (ok && !f64) {
       ok = make_tiling(p, kFloatTX, kFloatTallTY, cus, &ctx->tiling_tall);
       ctx->tall = ok && ctx->tiling_tall.chunk >= kFloatTallMinChunk;
     }

@@ -442,8 +442,8 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
   static_assert(MODEL == kModelSC || (!SOLID && !RECORD), "the colour-gradient step has no solids and no adjoint record");
-  static_assert(!TILED || (TX == kTileX && TY == kTileY && !SOLID && !RECORD),
-                "the tile-major layout serves the 64 x 4 step without solids or record");
+  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && !SOLID && !RECORD),
+                "the tile-major layout serves the 64-wide step without solids or record");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];

@@ -383,20 +383,22 @@ def test_full_size_reduced_storage_sampled_one_step(wname):
 
 
 
-def test_f32_tall_tiles_equal_the_64x4_tiles_bitwise():
-    """float32 without solids runs 64 x 8 tiles where their columns keep
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_float_tall_tiles_equal_the_64x4_tiles_bitwise(storage):
+    """Float storage without solids runs 64 x 8 tiles where their columns keep
     chunks of at least 64 planes; the node arithmetic does not depend on the
-    tile, so the result equals, bit for bit, the 64 x 4 kernel's (run here
-    through an all-fluid solid mask).  128 x 1020 x 64: 256 columns of 64 x 8
-    with a ragged last tile row, one 64-plane chunk each."""
+    tile, so the result equals, bit for bit, that of the 64 x 4 kernel with
+    solid handling (run here through an all-fluid solid mask).  128 x 1020 x
+    64: 256 columns of 64 x 8 with a ragged last tile row, one 64-plane chunk
+    each."""
     torch = _torch()
     shape = (64, 1020, 128)
     n = int(np.prod(shape))
-    _say(f"case f32 tall tiles vs 64x4 shape={shape}")
+    _say(f"case {storage} tall tiles vs 64x4 shape={shape}")
     a, b = synth.fluid_fields(shape, 0.02, 23)
     out = []
     for solid in (None, np.zeros(n, dtype=np.uint8)):
-        with P.Lattice(shape, tau=(0.8, 0.9), G=3.5, storage="f32") as lat:
+        with P.Lattice(shape, tau=(0.8, 0.9), G=3.5, storage=storage) as lat:
             lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy(), None, solid)
             lat.step(3)
             f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
@@ -444,29 +446,36 @@ def test_f64_tile_major_step_bitwise_equal_to_oracle(shape):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
-@pytest.mark.parametrize("shape", [(5, 8, 64), (3, 12, 128), (70, 4, 64)])
-def test_float_tile_major_step_equals_the_structure_of_arrays_step(shape, storage):
-    """Float storage without solids runs on the tile-major layout where nx is a
-    multiple of 64 and ny of 4; the node arithmetic does not depend on the
-    layout, so the populations equal, bit for bit, those of the structure-of-
-    arrays kernel (run through an all-fluid solid mask), with totals and a
-    population read between the steps."""
+@pytest.mark.parametrize("shape,with_solid", [((5, 8, 64), False), ((3, 12, 128), False), ((70, 4, 64), False),
+                                              ((6, 8, 64), True)])
+def test_float_tile_major_step_equals_the_structure_of_arrays_step(shape, with_solid, storage):
+    """Float storage runs on the tile-major layout where nx is a multiple of 64
+    and ny of 4.  lb_step_between steps snapshots, which are in the
+    structure-of-arrays layout, with the structure-of-arrays kernel; the node
+    arithmetic does not depend on the layout, so three steps each way give
+    the same populations bit for bit (with totals and a population read
+    between the tile-major steps)."""
     torch = _torch()
     n = int(np.prod(shape))
-    _say(f"case {storage} tile-major vs structure of arrays shape={shape}")
+    _say(f"case {storage} tile-major vs structure of arrays shape={shape} solid={with_solid}")
     a, b = synth.fluid_fields(shape, 0.05, 26)
-    out = []
-    for solid in (None, np.zeros(n, dtype=np.uint8)):
-        with P.Lattice(shape, tau=(0.8, 1.1), G=3.5, storage=storage) as lat:
-            lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy(), None, solid)
-            lat.step(2)
-            (_, _, _, _, _), nonfinite = lat.totals()
-            assert not nonfinite
-            lat.step(2)
-            f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
-            lat.get_populations(f)
-            lat.step(1)
-            lat.get_populations(f)
-            torch.cuda.synchronize()
-            out.append(f)
-    assert torch.equal(out[0], out[1])
+    solid = synth.solid_mask(shape, np.array([[30.0, 4.0, 3.0]]), 2.2).reshape(-1) if with_solid else None
+    with P.Lattice(shape, tau=(0.8, 1.1), G=3.5, storage=storage) as lat:
+        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy(), None, solid)
+        nb = P.lb_state_bytes(lat.ctx)
+        snaps = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(4)]
+        P.lb_save_state(lat.ctx, snaps[0])
+        for t in range(3):
+            P.lb_step_between(lat.ctx, snaps[t], snaps[t + 1])
+        lat.step(2)
+        (_, _, _, _, _), nonfinite = lat.totals()
+        assert not nonfinite
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        lat.step(1)
+        lat.get_populations(f)
+        P.lb_restore_state(lat.ctx, snaps[3])
+        g = torch.empty_like(f)
+        lat.get_populations(g)
+        torch.cuda.synchronize()
+    assert torch.equal(f, g)
