@@ -109,8 +109,17 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b,
 
 /* Advance n >= 0 steps.  One step: densities rho_k and pseudopotentials,
  * force, velocity-shifted BGK collision, pull streaming with bounce-back at
- * solid neighbours.  Enqueued; returns before completion.  Errors: LB_EINVAL
- * (n < 0), LB_ESTATE (no lb_set_fields / lb_set_populations yet), LB_EDEVICE. */
+ * solid neighbours.  Enqueued; returns before completion.
+ * Where nx is a multiple of 64 and ny of 4, the fused steps keep the
+ * populations in a tile-major order inside the library (one contiguous
+ * block per 64 x 4 tile and plane; float64 without solid nodes, float
+ * storage with or without): the first step after lb_set_fields,
+ * lb_set_populations, lb_restore_state or a call that reads the state
+ * (lb_moments, lb_get_populations, lb_totals, lb_save_state to host memory,
+ * the two-pass kernel) reorders the grid once, and those calls reorder it
+ * back (one read and one write of the grid each).  Results do not depend on
+ * the order.  Errors: LB_EINVAL (n < 0), LB_ESTATE (no lb_set_fields /
+ * lb_set_populations yet), LB_EDEVICE. */
 lb_status lb_step(lb_ctx* ctx, int32_t n);
 
 /* Moments of the current state: rho_a, rho_b [N] and the barycentric
@@ -201,10 +210,12 @@ typedef enum {
 lb_status lb_set_model(lb_ctx* ctx, int32_t model, double sigma, double beta);
 
 /* ---- Raw state snapshots (checkpointing) -------------------------------
- * A snapshot is the current population grid in the library's own storage
- * layout: lb_state_bytes() bytes, structure of arrays in the context's
- * storage format.  It is meant only for lb_restore_state, lb_step_between
- * and lb_adjoint_step of a context with the same parameters.
+ * A snapshot is the current population grid in the library's storage
+ * format: lb_state_bytes() bytes, structure of arrays (plane k * 19 + i at
+ * offset (k * 19 + i) * Npad elements, Npad = N rounded up to 128), whatever
+ * order lb_step keeps internally (lb_save_state to device memory writes it
+ * straight from that order).  It is meant only for lb_restore_state,
+ * lb_step_between and lb_adjoint_step of a context with the same parameters.
  * lb_save_state copies the current state to dst; lb_restore_state makes src
  * the current state.  on_device selects device or host memory.
  * Errors: LB_EINVAL, LB_ESTATE (save before any state), LB_EDEVICE. */
