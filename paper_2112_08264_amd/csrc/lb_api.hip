@@ -78,7 +78,7 @@ struct lb_ctx {
   void* psi = nullptr;     // [2][N] pseudopotential, arithmetic type
   uint8_t* mask = nullptr; // [N], allocated on first use
   bool has_solid = false;
-  bool tiled = false;  // the current population grid is in the tile-major layout (float64 only)
+  bool tiled = false;  // the current population grid is in the tile-major layout
   double* partial = nullptr;
   double* result = nullptr;
   int* flag = nullptr;
@@ -361,9 +361,10 @@ lb_status launch_fused(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* f
   });
 }
 
-// The staged float64 step on 64 x 4 tiles (either model) runs on the
-// tile-major layout (one contiguous block per tile plane instead of 38
-// streams).
+// The fused steps run on the tile-major layout (one contiguous block per
+// tile plane instead of 38 streams) where nx is a multiple of 64 and ny of 4:
+// the staged float64 step without solids (either model) and every float
+// step.
 bool tiled_ok(const lb_ctx* ctx) {
   if (ctx->p.nx % kTileX != 0 || ctx->p.ny % kTileY != 0 || 2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem >= 4294967296.0)
     return false;

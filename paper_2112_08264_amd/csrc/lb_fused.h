@@ -81,8 +81,8 @@ __device__ __forceinline__ int fused_work_item(int b, int total, int per_round) 
 }
 
 // ---------------------------------------------------------------------------
-// Tile-major population layout (fused steps without solids, nx a multiple
-// of 64 and ny of 4): population plane ki = k Q + i of node (x, y, z) at
+// Tile-major population layout (the fused steps where nx is a multiple of
+// 64 and ny of 4): population plane ki = k Q + i of node (x, y, z) at
 // element
 //   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
 //   tile = (y / 4) (nx / 64) + x / 64,
