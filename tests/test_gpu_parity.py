@@ -479,3 +479,26 @@ def test_float_tile_major_step_equals_the_structure_of_arrays_step(shape, with_s
         lat.get_populations(g)
         torch.cuda.synchronize()
     assert torch.equal(f, g)
+
+
+def test_f64_kernel_switches_between_layouts_bitwise():
+    """Switching between the staged step (tile-major layout) and the two-pass
+    step (structure of arrays) in the middle of a run reorders the state at
+    each switch; 2 + 2 + 1 steps stay bitwise equal to the oracle."""
+    torch = _torch()
+    shape = (5, 8, 64)
+    n = int(np.prod(shape))
+    _say(f"case f64 kernel switches shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.2, 27)
+    p = O.Params((0.8, 1.3), 3.5)
+    f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+    with P.Lattice(shape, tau=p.tau, G=p.G, kernel="fused_staged") as lat:
+        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
+        lat.step(2)
+        P.lb_set_kernel(lat.ctx, "two_pass")
+        lat.step(2)
+        P.lb_set_kernel(lat.ctx, "fused_staged")
+        lat.step(1)
+        lat.get_populations(f)
+        torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)), O.step(O.init_equilibrium(a, b), p, n=5))
