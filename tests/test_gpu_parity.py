@@ -442,7 +442,16 @@ def test_f64_tile_major_step_bitwise_equal_to_oracle(shape):
         lat.step(2)
         lat.get_populations(f)
         torch.cuda.synchronize()
-    assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)), O.step(f0, p, n=6))
+        assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)), O.step(f0, p, n=6))
+        # a host snapshot taken from the tile-major state (converted in place)
+        host = np.empty(int(P.lb_state_bytes(lat.ctx)) // 8)
+        P.lb_save_state(lat.ctx, host)
+        lat.step(3)
+        P.lb_restore_state(lat.ctx, host)
+        lat.step(1)
+        lat.get_populations(f)
+        torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)), O.step(f0, p, n=7))
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
