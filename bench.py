@@ -57,15 +57,19 @@ def log(msg: str) -> None:
 
 
 def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel="auto", timing_slots=True,
-              solid=None):
-    """Run one storage form; return a dict of timings."""
+              solid=None, repeats=0, repeat_steps=300):
+    """Run one storage form; return a dict of timings.  The starting totals
+    are read before the warmup: a read puts the state back in the structure-
+    of-arrays order, and the reorder into the step's own order then falls in
+    the warmup, not in the timed steps.  ``repeats`` more blocks of
+    ``repeat_steps`` steps follow the timed region, each timed on its own."""
     a, b = fields
     lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0, kernel=kernel)
     try:
         lat.set_fields(a, b, None, solid)
+        tot0, _ = lat.totals()
         lat.step(warmup)
         torch.cuda.synchronize()
-        tot0, _ = lat.totals()
         P.lb_timing(lat.ctx, timing_slots)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -83,12 +87,19 @@ def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel
             if cnt:
                 kernels[P.lb_timing_name(s)] = {"avg_ms": ms / cnt, "launches": cnt}
         P.lb_timing(lat.ctx, False)
+        repeat_ms = []
+        for _ in range(repeats):
+            e0.record()
+            lat.step(repeat_steps)
+            e1.record()
+            torch.cuda.synchronize()
+            repeat_ms.append(e0.elapsed_time(e1) / repeat_steps)
         tot1, nonfinite = lat.totals()
     finally:
         lat.close()
     mass_drift = max(abs(tot1[k] - tot0[k]) / abs(tot0[k]) for k in range(2))
     return {"event_ms": ev_ms, "wall_ms": (w1 - w0) * 1e3, "kernels": kernels, "nonfinite": nonfinite,
-            "mass_drift": mass_drift}
+            "mass_drift": mass_drift, "repeat_ms_per_step": repeat_ms}
 
 
 def _moments(torch, lat, n):
@@ -350,9 +361,9 @@ def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu
                         beta=w.beta)
         try:
             lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+            (a0, b0, *_), _ = lat.totals()  # before the warmup, which then takes the reorder into the step's order
             lat.step(warmup)
             torch.cuda.synchronize()
-            (a0, b0, *_), _ = lat.totals()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -627,7 +638,8 @@ def main(argv=None) -> int:
         log(f"bench: {w.spheres} spheres of radius {w.radius}, solid fraction {solid_fraction:.4f}")
 
     log(f"bench: {args.warmup} warmup + {args.steps} timed steps")
-    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields, kernel=args.kernel, solid=solid)
+    main_run = time_form(P, torch, w, w.storage, args.steps, args.warmup, fields, kernel=args.kernel, solid=solid,
+                         repeats=3)
     ms_step = main_run["event_ms"] / args.steps
     glups = w.nodes / (ms_step * 1e-3) / 1e9
     bpl = algorithmic_bytes_per_lup(w.storage)
@@ -722,6 +734,10 @@ def main(argv=None) -> int:
                    "tau": list(w.tau), "G": w.G, "rho0": list(w.rho0), "noise": w.amp, "seed": w.seed,
                    "boundary": "periodic", "solid_spheres": w.spheres, "solid_fraction": round(solid_fraction, 5)},
         "step_hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
+        # three more blocks of 300 steps after the timed region, for the median of repeated runs
+        "repeat_ms_per_step": [round(v, 4) for v in main_run["repeat_ms_per_step"]],
+        "repeat_median_ms_per_step": round(sorted(main_run["repeat_ms_per_step"])[1], 4)
+        if len(main_run["repeat_ms_per_step"]) == 3 else None,
         "fluid_glups": round(glups * (1.0 - solid_fraction), 4),
         "roofline": roofline,
         "copy_bandwidth": copy_bw,
