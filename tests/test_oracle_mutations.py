@@ -38,6 +38,27 @@ FORWARD = [
      "fs[k] = omc * f[k] + om[1 - k] * feq"),
 ]
 
+# Mistakes that the two physical pins of the readings (the linear spinodal
+# threshold and the relaxed flat interface) must catch on their own: each is
+# run against that pin alone, and again against all forward pins.
+THRESHOLD = "test_oracle_physics.py::test_spinodal_threshold_matches_linear_theory"
+FLAT = "test_oracle_physics.py::test_flat_interface_at_rest_has_zero_output_velocity"
+READINGS = [
+    ("velocity shift by (tau - 1/2) F", "a_k = (p.tau[k] * p.G) * psi_over_rho(rho[k], psi[k])",
+     "a_k = ((p.tau[k] - 0.5) * p.G) * psi_over_rho(rho[k], psi[k])", THRESHOLD),
+    ("pseudopotential with half the decay rate", "return psi_ref * (1.0 - exp_cw(-(rho / psi_ref)))",
+     "return psi_ref * (1.0 - exp_cw(-(0.5 * rho / psi_ref)))", THRESHOLD),
+    ("psi = rho (threshold alone)", "return psi_ref * (1.0 - exp_cw(-(rho / psi_ref)))", "return rho * 1.0",
+     THRESHOLD),
+    ("output velocity drops the 1/2", "ua = ((m[0][a] + m[1][a]) + 0.5 * (FA + FB)) / tot",
+     "ua = ((m[0][a] + m[1][a]) + (FA + FB)) / tot", FLAT),
+    ("output velocity subtracts the half force", "ua = ((m[0][a] + m[1][a]) + 0.5 * (FA + FB)) / tot",
+     "ua = ((m[0][a] + m[1][a]) - 0.5 * (FA + FB)) / tot", FLAT),
+    ("output velocity without the force term", "ua = ((m[0][a] + m[1][a]) + 0.5 * (FA + FB)) / tot",
+     "ua = (m[0][a] + m[1][a]) / tot", FLAT),
+]
+FORWARD = FORWARD + [(name, old, new) for name, old, new, _ in READINGS]
+
 ADJOINT = [
     ("drops the psi-stencil term", " - dpsi[k] * T", ""),
     ("common-velocity term sign", "- om[k] * (U * up).sum(axis=0) / D", "+ om[k] * (U * up).sum(axis=0) / D"),
@@ -126,6 +147,12 @@ def test_forward_pins_catch_planted_mistake(name, old, new):
     assert rc != 0, f"no pin failed for planted mistake: {name}"
 
 
+@pytest.mark.parametrize("name,old,new,pin", READINGS, ids=[m[0] for m in READINGS])
+def test_reading_pin_alone_catches_planted_mistake(name, old, new, pin):
+    rc = _run_mutant("lb_oracle.py", "oracle.lb_oracle", "lb_oracle", old, new, [os.path.join(TESTS, pin)])
+    assert rc != 0, f"{pin} did not catch the planted mistake: {name}"
+
+
 @pytest.mark.parametrize("name,old,new", ADJOINT, ids=[m[0] for m in ADJOINT])
 def test_adjoint_pins_catch_planted_mistake(name, old, new):
     tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
@@ -159,4 +186,13 @@ def test_unmutated_oracle_passes_through_the_same_runner():
     tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
     rc = _run_mutant("lb_adjoint.py", "oracle.lb_adjoint", "lb_adjoint", "import numpy as np", "import numpy as np",
                      tests)
+    assert rc == 0
+
+
+@pytest.mark.parametrize("pin", [THRESHOLD, FLAT])
+def test_reading_pins_pass_on_the_real_oracle_through_the_runner(pin):
+    # a pin selected by node id must run and pass unmutated (pytest's "no
+    # tests collected" would also be a non-zero exit)
+    rc = _run_mutant("lb_oracle.py", "oracle.lb_oracle", "lb_oracle", "import numpy as np", "import numpy as np",
+                     [os.path.join(TESTS, pin)])
     assert rc == 0

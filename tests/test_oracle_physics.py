@@ -191,3 +191,80 @@ def test_laplace_law_for_cylindrical_droplets():
     assert abs(icpt) < 0.1 * dps.min()
     # and the drop really is demixed
     assert np.all(dps > 0)
+
+
+# --------------------------------------------------------------------------
+# Linear spinodal threshold: pins the pseudopotential and the velocity shift
+# --------------------------------------------------------------------------
+def _psi_psiprime_at_one():
+    """psi(1) psi'(1) for psi = 1 - exp(-rho), written out from the closed form."""
+    e = np.exp(-1.0)
+    return (1.0 - e) * e
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+def test_spinodal_threshold_matches_linear_theory(tau):
+    """A symmetric mixture rho_A = rho_B = 1 demixes exactly where linear theory says.
+
+    Linearise around rho_A = rho_B = 1 with delta = rho_A - 1 = -(rho_B - 1).
+    The mass flux of component k averaged over the collision is
+    j_k = rho_k v_k - (tau - 1/2) c_s^2 grad rho_k (first moment of the BGK
+    non-equilibrium part), and the velocity shift puts rho_k v_k = rho_k u' +
+    tau F_k.  The stencil sum is S ~ c_s^2 grad psi, so F_A = -G psi(1) S(psi_B)
+    = G psi(1) psi'(1) c_s^2 grad delta.  Hence
+        d delta / dt = c_s^2 [(tau - 1/2) - tau G psi(1) psi'(1)] lap delta,
+    and a density-difference mode grows iff G > G_c = (tau - 1/2) / (tau psi psi').
+    The threshold tests the force's coefficient tau (a shift by (tau - 1/2) F
+    moves G_c to 1/(psi psi') = 4.30), the pseudopotential's value and slope
+    at rho = 1 and the stencil's c_s^2 together.
+    """
+    L, steps, eps = 32, 600, 1e-6
+    x = np.arange(L)
+    mode = np.cos(2.0 * np.pi * x / L)
+    Gc = (tau - 0.5) / (tau * _psi_psiprime_at_one())
+
+    def amplitude_ratio(G):
+        a = (1.0 + eps * mode).reshape(1, 1, L)
+        b = (1.0 - eps * mode).reshape(1, 1, L)
+        f = O.init_equilibrium(a, b)
+
+        def amp(f):
+            d = O.density(f[0]) - O.density(f[1])
+            return float(np.sum(d.ravel() * mode)) * 2.0 / L
+
+        a0 = amp(f)
+        f = O.step(f, O.Params((tau, tau), G), n=steps)
+        return amp(f) / a0
+
+    below, above = amplitude_ratio(0.95 * Gc), amplitude_ratio(1.05 * Gc)
+    assert below < 0.98, f"mode should decay 5% below G_c = {Gc:.4f}: ratio {below}"
+    assert above > 1.02, f"mode should grow 5% above G_c = {Gc:.4f}: ratio {above}"
+
+
+# --------------------------------------------------------------------------
+# Output velocity of a relaxed flat interface: pins the half-force term
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+def test_flat_interface_at_rest_has_zero_output_velocity(tau):
+    """At a relaxed flat interface nothing flows, so the output velocity vanishes.
+
+    In a steady state without flow the momentum averaged over the collision,
+    (m + m*) / 2 = m + F / 2 summed over the components, is zero, while the
+    pre-collision momentum sum_k m_k alone equals -sum_k F_k / 2, which is
+    large where the interface force acts.  The output velocity
+    (sum_k m_k + (F_A + F_B) / 2) / rho must therefore go to zero, and the bare
+    sum_k m_k / rho must not.
+    """
+    L, steps = 32, 2000
+    x = np.arange(L)
+    inside = (x >= L // 4) & (x < 3 * L // 4)
+    a = np.where(inside, 2.3, 0.06).reshape(1, 1, L).astype(np.float64)
+    b = np.where(inside, 0.06, 2.3).reshape(1, 1, L).astype(np.float64)
+    p = O.Params((tau, tau), 3.5)
+    f = O.step(O.init_equilibrium(a, b), p, n=steps)
+    ra, rb, u = O.moments(f, p)
+    bare = (O.momentum(f[0])[0] + O.momentum(f[1])[0]) / (ra + rb)
+    assert np.ptp(ra) > 2.0  # the interface is still sharp
+    assert np.max(np.abs(u[0])) <= 1e-5
+    assert np.max(np.abs(bare)) >= 1e-2
+    assert np.max(np.abs(u[1])) <= 1e-15 and np.max(np.abs(u[2])) <= 1e-15
