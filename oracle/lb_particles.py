@@ -51,29 +51,21 @@ Readings where the paper is silent, garbled, or defers to LBsoft:
 * Solid nodes hold zero populations.  The collision and the equilibrium are
   those of ``lb_single`` / ``lb_oracle``.
 
-Fixed order of the float64 particle sums (so that a GPU running one
-256-lane workgroup per particle reproduces them bit for bit):
+Particle sums.  The paper asks only that the force and torque on a particle
+be accumulated in double precision, because the link terms largely cancel
+(Sec. 5, particle paragraph).  This oracle takes the plain definition: each
+component of a particle's force, torque and covering momentum is the exact
+sum of its float64 terms, rounded once (math.fsum, correctly rounded).  Any
+other summation of the same n terms differs from it by at most
+(n - 1) u sum|t| + u |sum t|, u = 2^-53 (the bound ``sum_bound`` states).
 
-* Each particle's box has S = floor(2R) + 4 nodes per axis, from
-  lo_a = floor(r_pa - R) - 1.  Box nodes are numbered b = j_x + S (j_y + S j_z).
-* 256 partial sums are formed over a list of box nodes in increasing b:
-  partial l takes the list's entries l, l + 256, ... in order.
-  * Link sums: the list is the shell, the box nodes with
-    (R - 1.5)^2 <= (d_x d_x + d_y d_y) + d_z d_z <= R^2, d = node - r_p (a
-    node of the particle deeper in has all 18 neighbours inside it).  At each
-    entry the partial takes directions i = 1..18 in order, adding F_i and
-    r_b x F_i of every link from a fluid node into that node, if the node is
-    this particle's.
-  * Covering sums: the list is the whole box; each node adds its single term.
-* The partials are combined in four groups of 64 (l = 64 w .. 64 w + 63), each
-  by a butterfly: for s = 32, 16, ..., 1, a_l <- a_l + a_(l xor s).  The
-  group results A_0..A_3 (at l = 64 w) give (A_0 + A_1) + (A_2 + A_3).
-* Scalar arithmetic orders:
-  * W_i = (6 w_i) (rho (c_i . u_b)), with
-    u_b = v + (omega_y r_z - omega_z r_y, omega_z r_x - omega_x r_z, omega_x r_y - omega_y r_x).
-  * F_i = c_i ((g + g) + W_i) with g = f_ibar(x, t+1).
-  * T_i = (r_y F_z - r_z F_y, r_z F_x - r_x F_z, r_x F_y - r_y F_x).
-  * Distances: (d_x d_x + d_y d_y) + d_z d_z.
+Scalar arithmetic orders (the terms themselves):
+
+* W_i = (6 w_i) (rho (c_i . u_b)), with
+  u_b = v + (omega_y r_z - omega_z r_y, omega_z r_x - omega_x r_z, omega_x r_y - omega_y r_x).
+* F_i = c_i ((g + g) + W_i) with g = f_ibar(x, t+1).
+* T_i = (r_y F_z - r_z F_y, r_z F_x - r_x F_z, r_x F_y - r_y F_x).
+* Distances: (d_x d_x + d_y d_y) + d_z d_z.
 """
 
 from __future__ import annotations
@@ -214,24 +206,23 @@ def fluid_step(f: np.ndarray, tau: float, part: Particles, owner: np.ndarray):
     return out, rho
 
 
-LANES = 256
+def exact_sums(terms: np.ndarray) -> np.ndarray:
+    """Correctly rounded sum of terms [n][6] per component (math.fsum)."""
+    t = np.asarray(terms, dtype=np.float64).reshape(-1, 6)
+    return np.array([math.fsum(t[:, d]) for d in range(6)])
 
 
-def _lane_sum(terms: np.ndarray) -> np.ndarray:
-    """Sum terms [nodes][k][6] (box order, k terms per node) in the fixed order
-    of the module docstring."""
-    nb, k, d = terms.shape
-    pad = (-nb) % LANES
-    t = np.concatenate([terms, np.zeros((pad, k, d))]) if pad else terms
-    t = t.reshape(-1, LANES, k, d)
-    acc = np.zeros((LANES, d))
-    for row in range(t.shape[0]):
-        for i in range(k):
-            acc = acc + t[row, :, i, :]
-    idx = np.arange(LANES)
-    for s in (32, 16, 8, 4, 2, 1):
-        acc = acc + acc[idx ^ s]
-    return (acc[0] + acc[64]) + (acc[128] + acc[192])
+def sum_bound(terms: np.ndarray) -> np.ndarray:
+    """Per component, the largest difference between the correctly rounded sum
+    of terms [n][6] and any sum of them evaluated by n - 1 float64 additions
+    in any order: (n - 1) u sum|t| / (1 - (n - 1) u) + u |sum t|, u = 2^-53
+    (the standard bound for recursive summation, plus the final rounding of
+    the exact sum)."""
+    t = np.asarray(terms, dtype=np.float64).reshape(-1, 6)
+    u = 2.0 ** -53
+    n = max(t.shape[0] - 1, 0)
+    gamma = n * u / (1.0 - n * u)
+    return np.array([gamma * math.fsum(np.abs(t[:, d])) + u * abs(math.fsum(t[:, d])) for d in range(6)])
 
 
 def _box_nodes(part: Particles, p: int, shape):
@@ -244,41 +235,41 @@ def _box_nodes(part: Particles, p: int, shape):
     return (cx, cy, cz), (cz % nz, cy % ny, cx % nx)
 
 
-def link_forces(fnew: np.ndarray, rho: np.ndarray, part: Particles, owner: np.ndarray):
-    """Force and torque on each particle from the links of the step just made
-    (fnew = f(t+1), rho = rho(t), positions and velocities of step t)."""
+def link_terms(fnew: np.ndarray, rho: np.ndarray, part: Particles, owner: np.ndarray, p: int) -> np.ndarray:
+    """The float64 terms (F_i, r_b x F_i) [links][6] of particle p's links in
+    the step just made (fnew = f(t+1), rho = rho(t), positions and velocities
+    of step t): every link from a fluid node into a node of the particle."""
     shape = fnew.shape[-3:]
     nz, ny, nx = shape
+    (cx, cy, cz), (zw, yw, xw) = _box_nodes(part, p, shape)
+    mine = owner[zw, yw, xw] == p
+    zw, yw, xw = zw[mine], yw[mine], xw[mine]
+    out = []
+    for i in range(1, Q):
+        xf = (xw - C[i, 0]) % nx
+        yf = (yw - C[i, 1]) % ny
+        zf = (zw - C[i, 2]) % nz
+        link = owner[zf, yf, xf] == FLUID
+        if not np.any(link):
+            continue
+        xf, yf, zf = xf[link], yf[link], zf[link]
+        g = fnew[OPP[i], zf, yf, xf]
+        Wi, rb = _wall(i, xf.astype(np.float64), yf.astype(np.float64), zf.astype(np.float64),
+                       rho[zf, yf, xf], np.full(xf.shape, p), part, shape)
+        t = (g + g) + Wi
+        Fi = [C[i, a] * t for a in range(3)]
+        Ti = [rb[1] * Fi[2] - rb[2] * Fi[1], rb[2] * Fi[0] - rb[0] * Fi[2], rb[0] * Fi[1] - rb[1] * Fi[0]]
+        out.append(np.stack(Fi + Ti, axis=-1))
+    return np.concatenate(out) if out else np.zeros((0, 6))
+
+
+def link_forces(fnew: np.ndarray, rho: np.ndarray, part: Particles, owner: np.ndarray):
+    """Force and torque on each particle: the correctly rounded sums of its link terms."""
     P = part.pos.shape[0]
     F = np.zeros((P, 3))
     T = np.zeros((P, 3))
-    R2 = part.radius * part.radius
-    inner2 = (part.radius - 1.5) * (part.radius - 1.5) if part.radius > 1.5 else -1.0
     for p in range(P):
-        (cx, cy, cz), (zw, yw, xw) = _box_nodes(part, p, shape)
-        dx, dy, dz = cx - part.pos[p, 0], cy - part.pos[p, 1], cz - part.pos[p, 2]
-        d2 = (dx * dx + dy * dy) + dz * dz
-        shell = np.nonzero((d2 <= R2) & (d2 >= inner2))[0]  # increasing b
-        cx, cy, cz, zw, yw, xw = cx[shell], cy[shell], cz[shell], zw[shell], yw[shell], xw[shell]
-        mine = owner[zw, yw, xw] == p
-        terms = np.zeros((cx.size, Q - 1, 6))
-        for i in range(1, Q):
-            xf = (xw - C[i, 0]) % nx
-            yf = (yw - C[i, 1]) % ny
-            zf = (zw - C[i, 2]) % nz
-            link = mine & (owner[zf, yf, xf] == FLUID)
-            if not np.any(link):
-                continue
-            g = fnew[OPP[i], zf, yf, xf]
-            Wi, rb = _wall(i, xf.astype(np.float64), yf.astype(np.float64), zf.astype(np.float64),
-                           rho[zf, yf, xf], np.full(xf.shape, p), part, shape)
-            t = (g + g) + Wi
-            Fi = [C[i, a] * t for a in range(3)]
-            Ti = [rb[1] * Fi[2] - rb[2] * Fi[1], rb[2] * Fi[0] - rb[0] * Fi[2], rb[0] * Fi[1] - rb[1] * Fi[0]]
-            for a in range(3):
-                terms[:, i - 1, a] = np.where(link, Fi[a], 0.0)
-                terms[:, i - 1, 3 + a] = np.where(link, Ti[a], 0.0)
-        s = _lane_sum(terms)
+        s = exact_sums(link_terms(fnew, rho, part, owner, p))
         F[p] = s[:3]
         T[p] = s[3:]
     return F, T
@@ -300,39 +291,44 @@ def move(part: Particles, F: np.ndarray, T: np.ndarray, shape) -> Particles:
     return q
 
 
+def remap_terms(f: np.ndarray, part: Particles, owner_old: np.ndarray, owner_new: np.ndarray, rho0: float, p: int):
+    """Covering and uncovering of particle p (see the module docstring):
+    updates f in place at the nodes p covers or uncovers and returns the
+    momentum and moment terms [nodes][6] that the particle receives."""
+    (cx, cy, cz), (zw, yw, xw) = _box_nodes(part, p, f.shape[-3:])
+    covered = (owner_new[zw, yw, xw] == p) & (owner_old[zw, yw, xw] == FLUID)
+    uncovered = (owner_old[zw, yw, xw] == p) & (owner_new[zw, yw, xw] == FLUID)
+    d = [cx - part.pos[p, 0], cy - part.pos[p, 1], cz - part.pos[p, 2]]
+    terms = []
+    for b in np.nonzero(covered | uncovered)[0]:
+        z, y, x = zw[b], yw[b], xw[b]
+        db = [d[0][b], d[1][b], d[2][b]]
+        if covered[b]:
+            vals = f[:, z, y, x].copy()
+            f[:, z, y, x] = 0.0
+            sign = 1.0
+        else:
+            v, w = part.vel[p], part.omg[p]
+            ub = [v[0] + (w[1] * db[2] - w[2] * db[1]),
+                  v[1] + (w[2] * db[0] - w[0] * db[2]),
+                  v[2] + (w[0] * db[1] - w[1] * db[0])]
+            vals = O.equilibrium(np.float64(rho0), np.float64(ub[0]), np.float64(ub[1]), np.float64(ub[2]))
+            f[:, z, y, x] = vals
+            sign = -1.0
+        mom = O.momentum(vals.reshape(Q, 1))
+        mv = [sign * float(mom[a][0]) for a in range(3)]
+        terms.append(mv + [db[1] * mv[2] - db[2] * mv[1], db[2] * mv[0] - db[0] * mv[2],
+                           db[0] * mv[1] - db[1] * mv[0]])
+    return np.array(terms, dtype=np.float64).reshape(-1, 6)
+
+
 def remap(f: np.ndarray, part: Particles, owner_old: np.ndarray, owner_new: np.ndarray, rho0: float):
     """Covering and uncovering after the move (see the module docstring).
-    Modifies f in place and corrects the particle velocities."""
-    shape = f.shape[-3:]
-    P = part.pos.shape[0]
+    Modifies f in place and corrects the particle velocities by the correctly
+    rounded sums of the terms."""
     I = part.inertia
-    for p in range(P):
-        (cx, cy, cz), (zw, yw, xw) = _box_nodes(part, p, shape)
-        covered = (owner_new[zw, yw, xw] == p) & (owner_old[zw, yw, xw] == FLUID)
-        uncovered = (owner_old[zw, yw, xw] == p) & (owner_new[zw, yw, xw] == FLUID)
-        terms = np.zeros((cx.size, 1, 6))
-        d = [cx - part.pos[p, 0], cy - part.pos[p, 1], cz - part.pos[p, 2]]
-        for b in np.nonzero(covered | uncovered)[0]:
-            z, y, x = zw[b], yw[b], xw[b]
-            db = [d[0][b], d[1][b], d[2][b]]
-            if covered[b]:
-                vals = f[:, z, y, x].copy()
-                f[:, z, y, x] = 0.0
-                sign = 1.0
-            else:
-                v, w = part.vel[p], part.omg[p]
-                ub = [v[0] + (w[1] * db[2] - w[2] * db[1]),
-                      v[1] + (w[2] * db[0] - w[0] * db[2]),
-                      v[2] + (w[0] * db[1] - w[1] * db[0])]
-                vals = O.equilibrium(np.float64(rho0), np.float64(ub[0]), np.float64(ub[1]), np.float64(ub[2]))
-                f[:, z, y, x] = vals
-                sign = -1.0
-            mom = O.momentum(vals.reshape(Q, 1))
-            mv = [sign * float(mom[a][0]) for a in range(3)]
-            terms[b, 0, :3] = mv
-            terms[b, 0, 3:] = [db[1] * mv[2] - db[2] * mv[1], db[2] * mv[0] - db[0] * mv[2],
-                               db[0] * mv[1] - db[1] * mv[0]]
-        s = _lane_sum(terms)
+    for p in range(part.pos.shape[0]):
+        s = exact_sums(remap_terms(f, part, owner_old, owner_new, rho0, p))
         part.vel[p] = part.vel[p] + s[:3] / part.mass
         part.omg[p] = part.omg[p] + s[3:] / I
     return f

@@ -39,9 +39,12 @@ def isolated(centres, radius, shape, count, seed):
 def step_window(rho, tau, radius, mass, r, v, w, shape):
     """One oracle step of sphere (r, v, w) in a WINDOW^3 box cut from the
     lattice's initial density ``rho`` (fluid at rest).  Returns
-    (force, torque, pos, vel, omega, populations, node indices) with the
-    populations [19][k] at the window nodes within R + 3 of the centre and
-    their flat lattice indices [k]."""
+    (force, torque, pos, vel, omega, populations, node indices, bounds) with
+    the populations [19][k] at the window nodes within R + 3 of the centre,
+    their flat lattice indices [k], and ``bounds`` a dict: the summation
+    bounds "link" and "cover" [6] of the sphere's link and covering sums
+    (``PT.sum_bound``) and "uncovered" [k], the compared nodes the step
+    uncovers."""
     nz, ny, nx = shape
     j = np.arange(WINDOW)
     o = np.floor(r).astype(np.int64) - WINDOW // 2
@@ -49,13 +52,18 @@ def step_window(rho, tau, radius, mass, r, v, w, shape):
     here = PT.Particles(radius, mass, [r - o], [v], [w])
     f0, own0 = PT.init(rho[zi, yi, xi], here)
     f1, rho_t = PT.fluid_step(f0, tau, here, own0)
+    b_link = PT.sum_bound(PT.link_terms(f1, rho_t, here, own0, 0))
     F, T = PT.link_forces(f1, rho_t, here, own0)
     moved = PT.move(PT.Particles(radius, mass, [r], [v], [w]), F, T, shape)
     there = PT.Particles(radius, mass, [moved.pos[0] - o], moved.vel, moved.omg)
-    f1 = PT.remap(f1, there, own0, PT.owner_map((WINDOW,) * 3, there), 1.0)
+    own1 = PT.owner_map((WINDOW,) * 3, there)
+    b_cover = PT.sum_bound(PT.remap_terms(f1.copy(), there, own0, own1, 1.0, 0))
+    f1 = PT.remap(f1, there, own0, own1, 1.0)
     zw, yw, xw = np.meshgrid(j, j, j, indexing="ij")
     c = r - o
     near = ((xw - c[0]) ** 2 + (yw - c[1]) ** 2) + (zw - c[2]) ** 2 <= (radius + 3.0) ** 2
     bz, by, bx = zw[near], yw[near], xw[near]
     idx = (((bz + o[2]) % nz * ny + (by + o[1]) % ny) * nx + (bx + o[0]) % nx).ravel()
-    return F[0], T[0], moved.pos[0], there.vel[0], there.omg[0], f1[:, bz, by, bx], idx
+    unc = ((own0 != PT.FLUID) & (own1 == PT.FLUID))[bz, by, bx]
+    bounds = {"link": b_link, "cover": b_cover, "uncovered": unc}
+    return F[0], T[0], moved.pos[0], there.vel[0], there.omg[0], f1[:, bz, by, bx], idx, bounds

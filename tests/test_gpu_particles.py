@@ -2,9 +2,15 @@
 the C ABI) with the FP64 particle oracle (the paper's particle solver on the
 single-fluid step).
 
-float64 follows the oracle's operation order, including the fixed order of
-the particle force sums, and is held to bit equality for populations and
-particle state; float32 to bounds from its precision.
+The oracle sums each particle's force, torque and covering momentum exactly
+and rounds once (math.fsum); the GPU sums the same float64 terms in its own
+order.  After one step from a shared state the two forces and torques may
+differ by at most the summation bound of the terms (``PT.sum_bound``), and
+every population the sums do not reach is bitwise equal.  Over 15 steps the
+rounding differences of the sums propagate: states are held to the 1e-12
+relative-per-population bar and particle state to 1e-12 absolute (two
+summation orders of the oracle itself differ by about 1e-15 there).
+float32 is held to bounds from its precision.
 """
 
 import math
@@ -14,6 +20,7 @@ import numpy as np
 import pytest
 
 import paper_2112_08264_amd as P
+from oracle import lb_oracle as O
 from oracle import lb_particles as PT
 from oracle import lb_single as S
 import synth
@@ -74,22 +81,60 @@ CASES = {
 }
 
 
+U = 2.0 ** -53
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_f64_particles_bitwise_equal_to_oracle(name):
+def test_f64_particles_match_oracle_over_15_steps(name):
     shape, part = CASES[name]
-    _say(f"case particles f64 bitwise {name} shape={shape}")
+    _say(f"case particles f64 15 steps {name} shape={shape}")
     rho, u = _fluid(shape, 51)
     f, owner = PT.init(rho, part, u)
     ref, q, owner_end = PT.step(f, 0.8, part.copy(), owner, n=15)
     assert np.all(np.isfinite(ref))
     got, (pos, vel, omg, force, torque) = run_gpu(shape, 0.8, rho, u, part, 15)
     assert np.sum(owner_end != owner) > 0
-    assert np.array_equal(pos, q.pos)
-    assert np.array_equal(vel, q.vel)
-    assert np.array_equal(omg, q.omg)
-    assert np.array_equal(force, q.force)
-    assert np.array_equal(torque, q.torque)
-    assert np.array_equal(got, ref)
+    perr = O.population_error(got[None], ref[None])
+    serr = max(float(np.max(np.abs(a - b))) for a, b in ((pos, q.pos), (vel, q.vel), (omg, q.omg),
+                                                          (force, q.force), (torque, q.torque)))
+    _say(f"  population error {perr:.1e}, particle state {serr:.1e}")
+    assert perr <= 1e-12
+    assert serr <= 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_f64_particles_first_step_within_the_summation_bound(name):
+    """One step from the shared initial state.  The fluid step before the sums
+    is bitwise equal, so the GPU's force and torque must lie within the
+    summation bound of the oracle's own link terms, the velocities within
+    that bound over m (and I) plus the roundings of the two updates, and every
+    population not at a node uncovered in the step bitwise equal."""
+    shape, part = CASES[name]
+    _say(f"case particles f64 first step {name} shape={shape}")
+    rho, u = _fluid(shape, 51)
+    f, owner = PT.init(rho, part, u)
+    fnew, rho_t = PT.fluid_step(f, 0.8, part, owner)
+    nP = part.pos.shape[0]
+    bF = np.array([PT.sum_bound(PT.link_terms(fnew, rho_t, part, owner, p)) for p in range(nP)])
+    F, T = PT.link_forces(fnew, rho_t, part, owner)
+    q = PT.move(part, F, T, shape)
+    owner1 = PT.owner_map(shape, q)
+    bC = np.array([PT.sum_bound(PT.remap_terms(fnew.copy(), q, owner, owner1, 1.0, p)) for p in range(nP)])
+    ref = PT.remap(fnew, q, owner, owner1, 1.0)
+    got, (pos, vel, omg, force, torque) = run_gpu(shape, 0.8, rho, u, part, 1)
+    assert np.all(np.abs(force - F) <= bF[:, :3])
+    assert np.all(np.abs(torque - T) <= bF[:, 3:])
+    m, inertia = part.mass, part.inertia
+    tol_v = (bF[:, :3] + bC[:, :3]) / m + 8 * U * (np.abs(q.vel) + np.abs(F) / m + np.abs(part.vel))
+    tol_w = (bF[:, 3:] + bC[:, 3:]) / inertia + 8 * U * (np.abs(q.omg) + np.abs(T) / inertia + np.abs(part.omg))
+    assert np.all(np.abs(vel - q.vel) <= tol_v)
+    assert np.all(np.abs(omg - q.omg) <= tol_w)
+    assert np.all(np.abs(pos - q.pos) <= bF[:, :3] / m + 8 * U * (np.abs(q.pos) + 1.0))
+    uncovered = (owner != PT.FLUID) & (owner1 == PT.FLUID)
+    keep = ~uncovered
+    assert np.array_equal(got[:, keep], ref[:, keep])
+    if np.any(uncovered):
+        assert O.population_error(got[None][:, :, uncovered], ref[None][:, :, uncovered]) <= 1e-13
 
 
 def test_f64_resting_particle_is_the_fixed_solid_step():
@@ -231,8 +276,11 @@ def test_full_size_case3c_sampled_one_step(name):
     launches it, one step, checked sphere by sphere: 8 sampled spheres
     against the oracle stepped on a 32^3 window around each (the window
     reduction and its exactness are described in ``particle_window``).
-    float64 force, torque, position, velocities and the populations within
-    R + 3 of the centre are compared bit for bit.  Spheres across the
+    float64 force and torque are held to the summation bound of the
+    sphere's link terms, velocities and position to that bound propagated
+    through the leap-frog and the covering sums, and the populations within
+    R + 3 of the centre bit for bit (nodes the step uncovers, whose
+    populations carry the new velocity, to 1e-13).  Spheres across the
     periodic ends are covered by the small-box tests, against the
     whole-lattice oracle."""
     torch = _torch()
@@ -259,15 +307,24 @@ def test_full_size_case3c_sampled_one_step(name):
     f = f.view(19, n)
     errs = []
     for p in sample:
-        F, T, r1, vr, wr, ref, idx = PW.step_window(rho, w.tau[0], w.radius, mass, centres[p], vel[p], omg[p], shape)
+        F, T, r1, vr, wr, ref, idx, bd = PW.step_window(rho, w.tau[0], w.radius, mass, centres[p], vel[p], omg[p],
+                                                        shape)
         got = f[:, torch.from_numpy(idx).to("cuda")].cpu().numpy()
         if w.storage == "f64":
-            assert np.array_equal(force[p], F), p
-            assert np.array_equal(torque[p], T), p
-            assert np.array_equal(pos[p], r1), p
-            assert np.array_equal(v1[p], vr), p
-            assert np.array_equal(w1[p], wr), p
-            assert np.array_equal(got, ref), p
+            u53 = 2.0 ** -53
+            bF, bC = bd["link"], bd["cover"]
+            inertia = 0.4 * mass * w.radius * w.radius
+            assert np.all(np.abs(force[p] - F) <= bF[:3]), p
+            assert np.all(np.abs(torque[p] - T) <= bF[3:]), p
+            assert np.all(np.abs(v1[p] - vr) <= (bF[:3] + bC[:3]) / mass
+                          + 8 * u53 * (np.abs(vr) + np.abs(F) / mass + np.abs(vel[p]))), p
+            assert np.all(np.abs(w1[p] - wr) <= (bF[3:] + bC[3:]) / inertia
+                          + 8 * u53 * (np.abs(wr) + np.abs(T) / inertia + np.abs(omg[p]))), p
+            assert np.all(np.abs(pos[p] - r1) <= bF[:3] / mass + 8 * u53 * (np.abs(r1) + 1.0)), p
+            keep = ~bd["uncovered"]
+            assert np.array_equal(got[:, keep], ref[:, keep]), p
+            if np.any(bd["uncovered"]):
+                assert O.population_error(got[None][:, :, ~keep], ref[None][:, :, ~keep]) <= 1e-13, p
         else:
             # A sphere of radius 5.5 has about 2200 links.  Each adds 2 g, g a float32 population near 1/18
             # carrying a few float32 roundings (about 1e-8 each).  A random walk over them gives about 1e-6, and

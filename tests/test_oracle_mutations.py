@@ -105,7 +105,7 @@ PARTICLES = [
     ("particles: moving-wall term at unit density", "return (6.0 * W[i]) * (rho * cub), rb",
      "return (6.0 * W[i]) * cub, rb"),
     ("particles: link force counts the reflected population once", "t = (g + g) + Wi", "t = g + Wi"),
-    ("particles: covered momentum not handed over", "                sign = 1.0", "                sign = 0.0"),
+    ("particles: covered momentum not handed over", "            sign = 1.0", "            sign = 0.0"),
     ("particles: uncovered node starts at rest",
      "vals = O.equilibrium(np.float64(rho0), np.float64(ub[0]), np.float64(ub[1]), np.float64(ub[2]))",
      "vals = O.equilibrium(np.float64(rho0), np.float64(0.0), np.float64(0.0), np.float64(0.0))"),

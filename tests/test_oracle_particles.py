@@ -154,17 +154,29 @@ def test_uniform_flow_moving_with_the_particle_stays_uniform():
     assert np.sum(owner != owner0) > 20
 
 
-def test_fixed_order_particle_sums_are_sums():
+def test_particle_sums_are_correctly_rounded_and_the_bound_holds():
+    from fractions import Fraction
     rng = np.random.default_rng(5)
-    terms = rng.normal(size=(3375, 18, 6)) * (rng.random((3375, 18, 1)) < 0.05)
-    got = PT._lane_sum(terms)
+    # cancelling terms of mixed magnitude, as link terms are
+    terms = rng.normal(size=(2000, 6)) * 10.0 ** rng.integers(-8, 3, size=(2000, 6))
+    terms = np.concatenate([terms, -terms[:1500] * (1.0 + 1e-9)])
+    got = PT.exact_sums(terms)
+    bound = PT.sum_bound(terms)
     for d in range(6):
-        exact = math.fsum(terms[:, :, d].ravel())
-        assert abs(got[d] - exact) <= 64 * 2.0 ** -53 * np.sum(np.abs(terms[:, :, d])) + 1e-300
-    # the grouping is the one documented: a single term lands unchanged, wherever it is
-    one = np.zeros((3375, 18, 6))
-    one[2900, 7, 2] = 1.25
-    assert PT._lane_sum(one)[2] == 1.25
+        exact = sum((Fraction(float(t)) for t in terms[:, d]), Fraction(0))
+        assert got[d] == float(exact)  # Fraction -> float rounds to nearest
+        # any order of n - 1 float64 additions stays within the bound
+        for order in (np.arange(terms.shape[0]), np.arange(terms.shape[0])[::-1], rng.permutation(terms.shape[0])):
+            s = 0.0
+            for t in terms[order, d]:
+                s += float(t)
+            assert abs(s - got[d]) <= bound[d]
+        pair = terms[:, d].copy()
+        while pair.size > 1:  # pairwise tree
+            if pair.size % 2:
+                pair = np.append(pair, 0.0)
+            pair = pair[0::2] + pair[1::2]
+        assert abs(float(pair[0]) - got[d]) <= bound[d]
 
 
 def test_window_step_equals_the_whole_lattice_step():
@@ -190,7 +202,7 @@ def test_window_step_equals_the_whole_lattice_step():
     sample = PW.isolated(centres, R, shape, 8, 0)
     assert sample.size >= 3
     for p in sample:
-        F, T, r1, v1, w1, fw, idx = PW.step_window(rho, 1.0, R, mass, centres[p], vel[p], omg[p], shape)
+        F, T, r1, v1, w1, fw, idx, _ = PW.step_window(rho, 1.0, R, mass, centres[p], vel[p], omg[p], shape)
         assert np.array_equal(F, q.force[p]) and np.array_equal(T, q.torque[p]), p
         assert np.array_equal(r1, q.pos[p]) and np.array_equal(v1, q.vel[p]) and np.array_equal(w1, q.omg[p]), p
         assert np.array_equal(fw, f1[:, idx]), p
