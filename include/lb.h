@@ -331,6 +331,37 @@ lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double m
                             const double* vel, const double* omega);
 lb_status lb1_get_particles(lb1_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque);
 
+/* ---- Conserved totals of a snapshot, without allocating -----------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * totals of lb_totals computed from a caller-owned device snapshot, with no
+ * context.  Nothing is allocated: the per-workgroup partial sums live in a
+ * fixed device array inside the library (131,136 bytes per device, held
+ * until the process ends; the reduction grid is capped at 2048 workgroups,
+ * so every lattice fits).  The call calls no hipMalloc or hipFree.
+ *   params    nx, ny, nz, storage, rho0 (LB_F16_SHIFTED decoding), device
+ *             and stream are used; the other fields are ignored.
+ *   snapshot  device memory in the snapshot format of lb_save_state:
+ *             storage-typed, plane k * 19 + i at (k * 19 + i) * Npad
+ *             elements, Npad = N rounded up to 128.  Read only.
+ *   solid     device uint8 [N] (non-zero = solid, skipped), or NULL.
+ *   out       6 doubles: M_A, M_B, P_x, P_y, P_z (as lb_totals, same
+ *             reduction order, bitwise the same) and the count of
+ *             non-finite populations.  on_device = 1: device memory; the
+ *             call only enqueues on params->stream and returns LB_OK (the
+ *             caller reads out[5] for the non-finite count).  on_device = 0:
+ *             host memory; the call waits for the stream and returns
+ *             LB_ENONFINITE when out[5] != 0.
+ * Calls that overlap on one device share its array and race: issue them on
+ * one stream, or wait for one before the next.  The array keeps the last
+ * call's partial sums; each call writes the partials it reads first.
+ * Errors: LB_EINVAL (NULL params, snapshot or out; a size below 1; an
+ * unknown storage; non-finite rho0 with LB_F16_SHIFTED; more than
+ * 2^31 - 4097 nodes), LB_EDEVICE (bad device ordinal or a HIP failure),
+ * LB_ENONFINITE (host out only). */
+lb_status lb_snapshot_totals(const lb_params* params, const void* snapshot, const uint8_t* solid, double* out,
+                             int32_t on_device);
+
 /* Human-readable text for a status code. */
 const char* lb_strerror(lb_status status);
 

@@ -11,7 +11,7 @@ from .lb import (  # noqa: F401
     lb_record_bytes, lb_step_record,
     lb_get_populations, lb_restore_state, lb_save_state, lb_set_coupling, lb_set_model, LB_MODEL_SHAN_CHEN, LB_MODEL_COLOUR_GRADIENT, lb_state_bytes, lb_step_between, lb_moments, lb_params, lb_params_default, lb_set_fields,
     lb_set_kernel, lb_set_populations, lb_set_stream, lb_step, lb_strerror, lb_timing, lb_timing_name, lb_timing_read,
-    lb_timing_slots, lb_totals,
+    lb_timing_slots, lb_totals, lb_snapshot_totals,
     SingleFluid, lb1_create, lb1_destroy, lb1_get_populations, lb1_moments, lb1_set_fields, lb1_set_stream, lb1_step,
     lb1_totals, lb1_set_particles, lb1_get_particles,
 )

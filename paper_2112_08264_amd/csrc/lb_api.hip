@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -58,6 +59,7 @@ constexpr int kWideTX = 64;
 constexpr int kWideTY = 4;
 
 constexpr int kTotalsMaxBlocks = 2048;
+constexpr long long kSnapshotTotalsMaxNodes = 0x7fffffffLL - 4096;  // the 32-bit node index of the kernels
 
 struct TimedLaunch {
   int slot;
@@ -132,6 +134,13 @@ struct DeviceGuard {
 };
 
 int blocks_for(long long n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+
+// float16-shifted storage keeps f_i - w_i rho0_k; the other storages keep f.
+void set_shift(const lb_params& p, StepCoeffs* c) {
+  for (int k = 0; k < 2; ++k)
+    for (int i = 0; i < Q; ++i)
+      c->shift[k][i] = p.storage == LB_F16_SHIFTED ? static_cast<float>(weight<double>(i) * p.rho0[k]) : 0.0f;
+}
 
 lb_status dev_alloc(lb_ctx* ctx, void** ptr, size_t bytes) {
   if (hipMalloc(ptr, bytes) != hipSuccess) {
@@ -750,7 +759,96 @@ void free1(lb1_ctx* ctx) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device scratch of lb_snapshot_totals, the entry point that allocates
+// nothing: kTotalsMaxBlocks per-workgroup partial sums of eight doubles,
+// then eight result doubles (131,136 bytes).  Every device the library runs
+// it on holds its own copy until the process ends.  Host code never uses the
+// array's name as an address (on the host it names a stand-in, not device
+// memory): the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kTotalsMaxBlocks * 8 + 8];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[kScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+lb_status scratch_address(int device, double** out) {
+  if (device < 0 || device >= kScratchDevices) return LB_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch[device] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return LB_EDEVICE;
+    }
+    g_scratch[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch[device];
+  return LB_OK;
+}
+
+template <int ST>
+void snapshot_totals_launch(const void* f, const uint8_t* solid, const Geometry& g, const StepCoeffs& c, int blocks,
+                            double* partial, double* result, hipStream_t stream) {
+  using store = typename StorageTraits<ST>::store_t;
+  k_totals_partial<ST><<<blocks, kBlock, 0, stream>>>(static_cast<const store*>(f), solid, g, c, partial);
+  k_totals_final<<<1, kBlock, 0, stream>>>(partial, blocks, result);
+}
+
+}  // namespace
+
 extern "C" {
+
+lb_status lb_snapshot_totals(const lb_params* params, const void* snapshot, const uint8_t* solid, double* out,
+                             int32_t on_device) {
+  if (params == nullptr || snapshot == nullptr || out == nullptr) return LB_EINVAL;
+  const lb_params& p = *params;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return LB_EINVAL;
+  if (p.storage != LB_F64 && p.storage != LB_F32 && p.storage != LB_F16_SHIFTED) return LB_EINVAL;
+  if (p.storage == LB_F16_SHIFTED && !(is_finite(p.rho0[0]) && is_finite(p.rho0[1]))) return LB_EINVAL;
+  const long long N = static_cast<long long>(p.nx) * p.ny * p.nz;
+  if (N > kSnapshotTotalsMaxNodes) return LB_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) {
+    (void)hipGetLastError();
+    return LB_EDEVICE;
+  }
+  if (p.device < 0 || p.device >= ndev) return LB_EDEVICE;
+  DeviceGuard dg(p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  double* scr = nullptr;
+  {
+    const lb_status st = scratch_address(p.device, &scr);
+    if (st != LB_OK) return st;
+  }
+  Geometry g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.N = static_cast<int>(N);
+  g.Npad = (N + 127) / 128 * 128;
+  StepCoeffs c{};
+  set_shift(p, &c);
+  int blocks = blocks_for(N);
+  if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
+  double* partial = scr;                           // [blocks][8], each written before it is read
+  double* result = scr + kTotalsMaxBlocks * 8;     // host results pass through here
+  hipStream_t stream = static_cast<hipStream_t>(p.stream);
+  double* dst = on_device ? out : result;
+  if (p.storage == LB_F64) snapshot_totals_launch<LB_F64>(snapshot, solid, g, c, blocks, partial, dst, stream);
+  else if (p.storage == LB_F32) snapshot_totals_launch<LB_F32>(snapshot, solid, g, c, blocks, partial, dst, stream);
+  else snapshot_totals_launch<LB_F16_SHIFTED>(snapshot, solid, g, c, blocks, partial, dst, stream);
+  LB_HIP(hipGetLastError());
+  if (on_device) return LB_OK;
+  LB_HIP(hipMemcpyAsync(out, result, sizeof(double) * kTotals, hipMemcpyDeviceToHost, stream));
+  LB_HIP(hipStreamSynchronize(stream));
+  return out[5] != 0.0 ? LB_ENONFINITE : LB_OK;
+}
 
 void lb_params_default(lb_params* p) {
   if (p == nullptr) return;
@@ -869,9 +967,8 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
     c.omf[k] = static_cast<float>(c.om[k]);
     c.omcf[k] = static_cast<float>(c.omc[k]);
     c.tgf[k] = static_cast<float>(c.tg[k]);
-    for (int i = 0; i < Q; ++i)
-      c.shift[k][i] = p.storage == LB_F16_SHIFTED ? static_cast<float>(weight<double>(i) * p.rho0[k]) : 0.0f;
   }
+  set_shift(p, &c);
   c.G = p.G;
   c.psi_ref = p.psi_ref;
 

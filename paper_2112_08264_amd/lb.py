@@ -95,6 +95,7 @@ _SIGNATURES = [
     ("lb1_totals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     ("lb1_set_particles", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     ("lb1_get_particles", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("lb_snapshot_totals", ctypes.c_int, [ctypes.POINTER(lb_params), _P, _P, _P, ctypes.c_int32]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
 ]
@@ -361,6 +362,24 @@ def lb_device_bytes(ctx) -> int:
     b = ctypes.c_int64(0)
     _check(library().lb_device_bytes(ctx, ctypes.byref(b)), "lb_device_bytes")
     return b.value
+
+
+def lb_snapshot_totals(params: lb_params, snapshot, out, solid=None) -> int:
+    """Totals of a device snapshot into ``out`` (6 float64: host or device);
+    returns the status (LB_OK, or LB_ENONFINITE for a host ``out``)."""
+    nbytes = snapshot.numel() * snapshot.element_size() if type(snapshot).__module__.startswith("torch") else -1
+    ps, ds = _raw(snapshot, nbytes, "snapshot")
+    if not ds:
+        raise ValueError("lb_snapshot_totals needs a device snapshot")
+    n = int(params.nx) * int(params.ny) * int(params.nz)
+    pm, dm = _ptr(solid, "uint8", n, "solid")
+    if solid is not None and not dm:
+        raise ValueError("lb_snapshot_totals needs a device solid mask")
+    po, do = _ptr(out, "float64", 6, "out")
+    st = library().lb_snapshot_totals(ctypes.byref(params), ps, pm, po, do)
+    if st not in (LB_OK, LB_ENONFINITE):
+        _check(st, "lb_snapshot_totals")
+    return st
 
 
 # ---------------------------------------------------------------------------

@@ -114,3 +114,24 @@ def test_single_fluid_calls_reject_null_context():
     assert lib.lb1_get_particles(None, None, None, None, None, None) == P.LB_EINVAL
     assert lib.lb1_destroy(None) == P.LB_OK
 
+
+
+def test_snapshot_totals_rejects_bad_arguments_without_a_device():
+    lib = P.library()
+    buf = (ctypes.c_double * 8)()
+    p = P.lb_params_default()
+    out = (ctypes.c_double * 6)()
+    assert lib.lb_snapshot_totals(None, buf, None, out, 0) == P.LB_EINVAL
+    assert lib.lb_snapshot_totals(ctypes.byref(p), None, None, out, 0) == P.LB_EINVAL
+    assert lib.lb_snapshot_totals(ctypes.byref(p), buf, None, None, 0) == P.LB_EINVAL
+    for field, value in (("nx", 0), ("nz", -1), ("storage", 9)):
+        q = P.lb_params_default()
+        setattr(q, field, value)
+        assert lib.lb_snapshot_totals(ctypes.byref(q), buf, None, out, 0) == P.LB_EINVAL, field
+    q = P.lb_params_default()
+    q.nx, q.ny, q.nz = 2048, 2048, 1024  # beyond the 32-bit node index
+    assert lib.lb_snapshot_totals(ctypes.byref(q), buf, None, out, 0) == P.LB_EINVAL
+    q = P.lb_params_default()
+    q.storage = P.LB_F16_SHIFTED
+    q.rho0[0] = float("nan")
+    assert lib.lb_snapshot_totals(ctypes.byref(q), buf, None, out, 0) == P.LB_EINVAL
