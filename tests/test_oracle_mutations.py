@@ -113,6 +113,21 @@ PARTICLES = [
      "Ti = [rb[2] * Fi[1] - rb[1] * Fi[2], rb[0] * Fi[2] - rb[2] * Fi[0], rb[1] * Fi[0] - rb[0] * Fi[1]]"),
 ]
 
+CG_PARTICLES = [
+    ("cg particles: wall wetted by fluid 1", "t = W[i] * np.where(nb_solid, theta, nb)",
+     "t = W[i] * np.where(nb_solid, 1.0, nb)"),
+    ("cg particles: wall as a half-and-half mixture", "t = W[i] * np.where(nb_solid, theta, nb)",
+     "t = W[i] * np.where(nb_solid, 0.0, nb)"),
+    ("cg particles: wall term with the mixture density per component",
+     "Wi, _ = PT._wall(i, x, y, z, rho[k], pidx, part, shape)",
+     "Wi, _ = PT._wall(i, x, y, z, rho[0] + rho[1], pidx, part, shape)"),
+    ("cg particles: covering and uncovering exchange one component only", "mom = O.momentum(vals.reshape(Q, 1))",
+     "mom = O.momentum(vals.reshape(Q, 1) * (k == 0))"),
+    ("cg particles: uncovered node at the other component's density",
+     "vals = O.equilibrium(np.float64(rho0[k]),", "vals = O.equilibrium(np.float64(rho0[1 - k]),"),
+    ("cg particles: link force counts the reflected population once", "t = (g + g) + Wi", "t = g + Wi"),
+]
+
 RUNNER = r"""
 import importlib.util, sys
 sys.path.insert(0, {root!r})
@@ -181,6 +196,13 @@ def test_particle_pins_catch_planted_mistake(name, old, new):
     assert rc != 0, f"no pin failed for planted mistake: {name}"
 
 
+@pytest.mark.parametrize("name,old,new", CG_PARTICLES, ids=[m[0] for m in CG_PARTICLES])
+def test_cg_particle_pins_catch_planted_mistake(name, old, new):
+    tests = [os.path.join(TESTS, "test_oracle_cg_particles.py")]
+    rc = _run_mutant("lb_cg_particles.py", "oracle.lb_cg_particles", "lb_cg_particles", old, new, tests)
+    assert rc != 0, f"no pin failed for planted mistake: {name}"
+
+
 def test_unmutated_oracle_passes_through_the_same_runner():
     # the runner itself must not fail on the real oracle
     tests = [os.path.join(TESTS, "test_oracle_adjoint.py")]
@@ -195,4 +217,11 @@ def test_reading_pins_pass_on_the_real_oracle_through_the_runner(pin):
     # tests collected" would also be a non-zero exit)
     rc = _run_mutant("lb_oracle.py", "oracle.lb_oracle", "lb_oracle", "import numpy as np", "import numpy as np",
                      [os.path.join(TESTS, pin)])
+    assert rc == 0
+
+
+def test_unmutated_cg_particle_oracle_passes_through_the_runner():
+    tests = [os.path.join(TESTS, "test_oracle_cg_particles.py")]
+    rc = _run_mutant("lb_cg_particles.py", "oracle.lb_cg_particles", "lb_cg_particles", "import numpy as np",
+                     "import numpy as np", tests)
     assert rc == 0
