@@ -190,8 +190,46 @@ def accuracy_run(P, torch, w, fields, checkpoints=(1, 10, 100, 1000), restart=(1
             out[st] = {"trajectory": rows, "restart": rrows}
         finally:
             lat.close()
+    # first step at which each form's max |drho| passes the 1e-3 target:
+    # along the trajectory from the initial state, and after the restart
+    for st in ("f32", "f16s"):
+        out[st]["first_step_over_1e-3"] = first_step_over(P, torch, w, fields, st, None, limit=400)
+        out[st]["restart_first_step_over_1e-3"] = first_step_over(P, torch, w, fields, st, pop, limit=10)
     del pop
     return out
+
+
+def first_step_over(P, torch, w, fields, storage, start_pop=None, limit=400, bar=1e-3):
+    """Step the float64 path and one reduced form side by side, from the
+    initial fields or from the float64 populations ``start_pop``, and return
+    the first step after which max |drho_k| exceeds ``bar`` (None if it does
+    not within ``limit`` steps) with the error after every step."""
+    a, b = fields
+    n = w.nodes
+    lats = [P.Lattice(w.shape, tau=w.tau, G=w.G, storage=st, device=0) for st in ("f64", storage)]
+    errs = []
+    first = None
+    try:
+        for lat in lats:
+            if start_pop is None:
+                lat.set_fields(a, b)
+            else:
+                lat.set_populations(start_pop)
+        for s in range(1, limit + 1):
+            for lat in lats:
+                lat.step(1)
+            ref = _moments(torch, lats[0], n)
+            got = _moments(torch, lats[1], n)
+            e = float(torch.maximum((got[0] - ref[0]).abs(), (got[1] - ref[1]).abs()).max())
+            errs.append(e)
+            if e > bar:
+                first = s
+                break
+    finally:
+        for lat in lats:
+            lat.close()
+    return {"bar": bar, "first_step": first, "limit": limit, "max_drho_per_step": [float(f"{e:.3e}") for e in errs]
+            if len(errs) <= 20 else [float(f"{e:.3e}") for e in errs[-5:]], "steps_run": len(errs)}
 
 
 def oracle_sample(name, w, planes, steps, make_state, advance):
@@ -244,6 +282,7 @@ def single_fluid_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu: b
         bpl = 19 * 2 * BYTES_PER_VALUE[st]
         out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
                    "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4), "mass_drift": abs(m1 - m0) / m0,
+                   **traffic_fields(w.name, "k1_step", ms),
                    "nonfinite": nonfinite}
     if cpu:
         from oracle import lb_single as S
@@ -269,7 +308,9 @@ def spheres_run(P, torch, synth, steps: int = 100, warmup: int = 10):
     ms = r["event_ms"] / steps
     glups = w.nodes / (ms * 1e-3) / 1e9
     bpl = algorithmic_bytes_per_lup(w.storage)
-    return {"workload": w.name, "lattice": list(w.shape), "spheres": w.spheres, "solid_fraction": round(phi, 5),
+    fused = r["kernels"].get("fused", {}).get("avg_ms")
+    return {**traffic_fields(w.name, "fused", fused),
+            "workload": w.name, "lattice": list(w.shape), "spheres": w.spheres, "solid_fraction": round(phi, 5),
             "glups": round(glups, 4), "fluid_glups": round(glups * (1.0 - phi), 4), "ms_per_step": round(ms, 4),
             "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4), "mass_drift": r["mass_drift"],
             "nonfinite": r["nonfinite"]}
@@ -286,9 +327,9 @@ def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool
     scattered accesses."""
     import numpy as np
 
-    out = {"lattice": [256, 256, 256], "radius": 5.5,
-           "paper_context": "34.6 / 37.6 / 56 ms per step (0.484 / 0.446 / 0.299 GLUPS) at 0.1 / 1 / 10% on one V100, "
-                            "single precision, colour-gradient fluid with particles (Sec. 5, particle table)"}
+    out = {"lattice": [256, 256, 256], "radius": 5.5, "fluid": "single fluid",
+           "paper_context": "none like for like: the paper times particles in the two-fluid colour-gradient "
+                            "model only (block cg_particles)"}
     base = {}
     for name in ("case3a_256_f32", "case3b_256_f32", "case3c_256_f32", "case3c_256_f64"):
         w = synth.WORKLOADS[name]
@@ -324,6 +365,9 @@ def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool
         phi = w.spheres * (4.0 / 3.0) * np.pi * w.radius ** 3 / w.nodes
         # fluid bytes per node: 19 populations read and written, plus the owner word
         bpl = 2 * 19 * (4 if w.storage == "f32" else 8) + 4
+        if name == "case3c_256_f32":
+            out["traffic_k1p_step"] = traffic_fields(name, "k1p_step")
+            out["traffic_force_move"] = traffic_fields(name, "force_move")
         out[name] = {"spheres": w.spheres, "volume_fraction": round(phi, 5), "glups": round(w.nodes / (ms * 1e-3) / 1e9, 4),
                      "ms_per_step": round(ms, 4), "no_particles_ms_per_step": round(base[w.storage], 4),
                      "overhead": round(ms / base[w.storage] - 1.0, 4), "fluid_bytes_per_lup": bpl,
@@ -344,6 +388,92 @@ def particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool
         out["cpu_baseline"] = {"value": 64 ** 3 * 2 / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
                                "sample": f"2 steps of the float64 NumPy particle oracle on a 64^3 box with {count} "
                                          f"spheres of radius 5.5 (10%), {dt:.1f} s"}
+    return out
+
+
+def cg_particles_run(P, torch, synth, steps: int = 100, warmup: int = 10, cpu: bool = False):
+    """The paper's case 3: moving rigid spheres (radius 5.5, 2.2 times the
+    fluid density, at rest at the start) in the two immiscible fluids of
+    case 2 (colour gradient, every node pure red or pure blue) on 256^3, at
+    the volume fractions 0.1%, 1% and 10%, float32 (and float64 at 10%).
+    GLUPS count every node.  The overhead is the time per step over that of
+    the same fluid without particles (which runs on the tile-major layout);
+    hbm_frac_fluid prices the step at the fluid's own bytes (38 populations
+    each way and the owner word per node) against 8 TB/s."""
+    import numpy as np
+
+    out = {"lattice": [256, 256, 256], "radius": 5.5, "fluid": "colour gradient, two components",
+           "paper_context": "34.6 / 37.6 / 56 ms per step (0.484 / 0.446 / 0.299 GLUPS) at 0.1 / 1 / 10% on one "
+                            "V100, single precision (Sec. 5, particle table)"}
+    base = {}
+    for name in ("case3cg_a_256_f32", "case3cg_b_256_f32", "case3cg_c_256_f32", "case3cg_c_256_f64"):
+        w = synth.WORKLOADS[name]
+        r1, r2 = synth.colour_fields(w.shape, w.seed)
+        centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+        lat = P.Lattice(w.shape, tau=w.tau, storage=w.storage, rho0=w.rho0, device=0, model="colour_gradient",
+                        sigma=w.sigma, beta=w.beta)
+        try:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            if w.storage not in base:
+                lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+                lat.step(warmup)
+                torch.cuda.synchronize()
+                e0.record()
+                lat.step(steps)
+                e1.record()
+                torch.cuda.synchronize()
+                base[w.storage] = e0.elapsed_time(e1) / steps
+            lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+            lat.set_particles(centres, w.radius, synth.particle_mass(w.radius))
+            tot0, _ = lat.totals()
+            lat.step(warmup)
+            torch.cuda.synchronize()
+            P.lb_timing(lat.ctx, True)
+            e0.record()
+            lat.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            kernels = {}
+            for sl in range(P.lb_timing_slots()):
+                kms, cnt = P.lb_timing_read(lat.ctx, sl)
+                if cnt:
+                    kernels[P.lb_timing_name(sl)] = {"avg_ms": round(kms / cnt, 4), "launches": cnt}
+            P.lb_timing(lat.ctx, False)
+            tot1, nonfinite = lat.totals()
+        finally:
+            lat.close()
+        phi = w.spheres * (4.0 / 3.0) * np.pi * w.radius ** 3 / w.nodes
+        bpl = 2 * 2 * 19 * (4 if w.storage == "f32" else 8) + 4
+        if name == "case3cg_c_256_f32":
+            out["traffic_fused"] = traffic_fields(name, "fused", kernels.get("fused", {}).get("avg_ms"))
+            out["traffic_force_move"] = traffic_fields(name, "force_move", kernels.get("part_force", {}).get("avg_ms"))
+        out[name] = {"spheres": w.spheres, "volume_fraction": round(phi, 5),
+                     "glups": round(w.nodes / (ms * 1e-3) / 1e9, 4), "ms_per_step": round(ms, 4),
+                     "no_particles_ms_per_step": round(base[w.storage], 4),
+                     "overhead": round(ms / base[w.storage] - 1.0, 4), "fluid_bytes_per_lup": bpl,
+                     "hbm_frac_fluid": round(bpl * w.nodes / (ms * 1e-3) / 8e12, 4),
+                     "kernels_timed_separately": kernels,
+                     "mass_change": [(tot1[k] - tot0[k]) / tot0[k] for k in range(2)], "nonfinite": nonfinite}
+    if cpu:
+        from oracle import lb_cg_particles as CP
+        from oracle import lb_particles as PT
+
+        sh = (48, 48, 48)
+        count = 16  # 10% of a 48^3 box in spheres of radius 5.5
+        w = synth.WORKLOADS["case3cg_c_256_f64"]
+        centres = synth.sphere_centres(sh, count, w.radius, w.sphere_seed)
+        r1, r2 = synth.colour_fields(sh, w.seed)
+        part = PT.Particles(w.radius, synth.particle_mass(w.radius), centres, None, None)
+        f, owner = CP.init(r1, r2, part)
+        p = CP.Params(w.tau, w.sigma, w.beta, w.rho0)
+        t0 = time.perf_counter()
+        CP.step(f, p, part, owner, n=2)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 48 ** 3 * 2 / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"2 steps of the float64 NumPy colour-gradient particle oracle on a 48^3 box "
+                                         f"with {count} spheres of radius 5.5 (10%), {dt:.1f} s"}
     return out
 
 
@@ -377,7 +507,7 @@ def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu
         glups = w.nodes / (ms * 1e-3) / 1e9
         bpl = 2 * 19 * 2 * BYTES_PER_VALUE[st]
         out[st] = {"glups": round(glups, 4), "ms_per_step": round(ms, 4), "bytes_per_lup": bpl,
-                   "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4),
+                   "hbm_frac": round(bpl * glups / HBM_PEAK_GBS, 4), **traffic_fields(w.name, "fused", ms),
                    "mass_drift": max(abs(a1 - a0) / a0, abs(b1 - b0) / b0), "nonfinite": nonfinite}
     if cpu:
         from oracle import lb_cg as CG
@@ -391,46 +521,127 @@ def colour_gradient_run(P, torch, synth, steps: int = 200, warmup: int = 10, cpu
     return out
 
 
-def adjoint_run(P, torch, synth, every: int = 50):
+def adjoint_run(P, torch, synth, every: int = 50, fd: bool = True):
     """Forward (with checkpoint saves) and backward (recompute + adjoint) of
-    J = sum (rho_A(T) - target)^2 on the 128^3 float32 gradient workload."""
+    J = sum (rho_A(T) - target)^2 on the 128^3, 500-step gradient workload,
+    in float32 and in float64 storage.
+
+    * ratio: backward (seeding, restores, recomputation, adjoint steps,
+      read-out) over forward (the steps and checkpoint saves), both device
+      time; also over the plain 500 forward steps alone.
+    * float32 against float64: the float32 adjoint's dJ/drho_A(0) at 16
+      sites (seed 5) and over the whole field, and its dJ/dG, relative to the
+      float64 adjoint.
+    * float64 against differences: fourth-order central differences of the
+      float64 forward (h = 2e-5, objective summed exactly) at the same 16
+      sites and for G; the error of each site relative to the largest sampled
+      |gradient| (the normalisation of the 1e-6 target) and to its own value.
+    """
+    import math
+
+    import numpy as np
+
     from paper_2112_08264_amd import autograd as AG
 
     w = synth.WORKLOADS["adjoint128_f32"]
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
-    target = torch.tensor(synth.smooth_target(w.shape, 4), device="cuda")
-    spec = AG.Spec(shape=w.shape, tau=w.tau, steps=w.steps, every=every, storage=w.storage)
+    target_np = synth.smooth_target(w.shape, 4)
+    target = torch.tensor(target_np, device="cuda")
+    sites = synth.sample_sites(w.shape, 16, 5)
 
-    def once():
+    def gradient(storage):
+        spec = AG.Spec(shape=w.shape, tau=w.tau, steps=w.steps, every=every, storage=storage)
         ra = torch.tensor(a, device="cuda", requires_grad=True)
         rb = torch.tensor(b, device="cuda")
         G = torch.tensor(w.G, dtype=torch.float64, requires_grad=True)
         out = AG.final_density(ra, G, rb, spec)
         J = ((out - target) ** 2).sum()
         J.backward()
-        return float(J), float(G.grad), float(ra.grad.abs().max())
+        return float(J), ra.grad.detach().cpu().numpy(), float(G.grad)
 
-    once()  # warm-up (allocations, code objects)
-    J, dG, gmax = once()
-    fwd, bwd = AG.timings.forward_ms, AG.timings.backward_ms
-    # plain forward steps for reference
-    lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=w.storage, device=0)
-    try:
-        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
-        lat.step(10)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        lat.step(w.steps)
-        e1.record()
-        torch.cuda.synchronize()
-        plain = e0.elapsed_time(e1)
-    finally:
-        lat.close()
-    return {"workload": w.name, "steps": w.steps, "checkpoint_every": every, "forward_ms": round(fwd, 3),
-            "backward_ms": round(bwd, 3), "ratio": round(bwd / fwd, 3), "plain_forward_ms": round(plain, 3),
-            "J": J, "dJ_dG": dG, "max_abs_dJ_drhoA0": gmax}
+    def plain_forward_ms(storage):
+        lat = P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage, device=0)
+        try:
+            lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
+            lat.step(10)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lat.step(w.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
+        finally:
+            lat.close()
+
+    forms = {}
+    grads = {}
+    for storage in ("f32", "f64"):
+        gradient(storage)  # warm-up (allocations, code objects)
+        J, ga, dG = gradient(storage)
+        fwd, bwd = AG.timings.forward_ms, AG.timings.backward_ms
+        plain = plain_forward_ms(storage)
+        grads[storage] = (J, ga, dG)
+        forms[storage] = {"forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3), "ratio": round(bwd / fwd, 3),
+                          "plain_forward_ms": round(plain, 3), "ratio_to_plain_forward": round(bwd / plain, 3),
+                          "J": J, "dJ_dG": dG, "max_abs_dJ_drhoA0": float(np.max(np.abs(ga)))}
+    J32, g32, dG32 = grads["f32"]
+    J64, g64, dG64 = grads["f64"]
+    at = [(int(x), int(y), int(z)) for x, y, z in sites]
+    s64 = np.array([g64[z, y, x] for x, y, z in at])
+    s32 = np.array([g32[z, y, x] for x, y, z in at])
+    f32_vs_f64 = {"sites": 16, "site_seed": 5,
+                  "max_site_error_over_max_site_gradient": float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64))),
+                  "max_site_relative_error": float(np.max(np.abs(s32 - s64) / np.abs(s64))),
+                  "field_max_error_over_max_gradient": float(np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))),
+                  "dJ_dG_relative_error": abs(dG32 - dG64) / abs(dG64),
+                  "J_relative_error": abs(J32 - J64) / abs(J64)}
+    out = {"workload": w.name, "steps": w.steps, "checkpoint_every": every, "forms": forms,
+           "f32_vs_f64_adjoint": f32_vs_f64,
+           "traffic_adj_local": traffic_fields(w.name, "adj_local"), "traffic_adj_r": traffic_fields(w.name, "adj_r"),
+           # the float32 form is the workload's own storage; kept at the top level for continuity
+           "forward_ms": forms["f32"]["forward_ms"], "backward_ms": forms["f32"]["backward_ms"],
+           "ratio": forms["f32"]["ratio"]}
+    if not fd:
+        return out
+    tt = target.view(-1)
+
+    def J_of(ra, G=w.G):
+        lat = P.Lattice(w.shape, tau=w.tau, G=G, storage="f64", device=0)
+        try:
+            lat.set_fields(ra.reshape(-1).copy(), b.reshape(-1).copy())
+            lat.step(w.steps)
+            r = torch.empty(ra.size, dtype=torch.float64, device="cuda")
+            lat.moments(rho_a=r)
+        finally:
+            lat.close()
+        return math.fsum(((r - tt) ** 2).cpu().numpy())
+
+    def d4(f, h):
+        return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+    rows = []
+    for x, y, z in at:
+        def f(eps, x=x, y=y, z=z):
+            ap = a.copy()
+            ap[z, y, x] += eps
+            return J_of(ap)
+        rows.append((d4(f, 2e-5), float(g64[z, y, x])))
+    fdG = d4(lambda eps: J_of(a, w.G + eps), 1e-5)
+    fdv = np.array([r[0] for r in rows])
+    adj = np.array([r[1] for r in rows])
+    err = np.abs(fdv - adj)
+    out["f64_vs_differences"] = {
+        "sites": 16, "h": 2e-5, "order": 4,
+        "max_site_error_over_max_site_gradient": float(np.max(err) / np.max(np.abs(fdv))),
+        "median_site_error_over_max_site_gradient": float(np.median(err) / np.max(np.abs(fdv))),
+        "max_site_relative_error": float(np.max(err / np.abs(fdv))),
+        "median_site_relative_error": float(np.median(err / np.abs(fdv))),
+        "dJ_dG_relative_error": abs(fdG - dG64) / abs(fdG),
+        "max_abs_site_gradient": float(np.max(np.abs(fdv))),
+        "min_abs_site_gradient": float(np.min(np.abs(fdv)))}
+    return out
 
 
 def copy_calibration(torch, nbytes: int = 2 << 30, reps: int = 5):
@@ -505,6 +716,131 @@ def cpu_baseline(w, fields_fn):
     }
 
 
+# Kernels whose HBM traffic is measured (rocprofv3 FETCH_SIZE / WRITE_SIZE):
+# target -> (workload, {key in profiles/traffic.json: kernel symbol substring}).
+PROFILE_TARGETS = {
+    "sc_f64": ("spinodal256_f64", {"fused": "k_fused_pair<"}),
+    "sc_f32": ("spinodal256_f32", {"fused": "k_fused<"}),
+    "sc_f16s": ("spinodal256_f16s", {"fused": "k_fused<"}),
+    "cg_f32": ("case2_256_f32", {"fused": "k_fused_pair<"}),
+    "cg_f64": ("case2_256_f64", {"fused": "k_fused_pair<"}),
+    "single_f32": ("case1_256_f32", {"k1_step": "k1_step<"}),
+    "single_f64": ("case1_256_f64", {"k1_step": "k1_step<"}),
+    "spheres_f32": ("spheres512_f32", {"fused": "k_fused<"}),
+    "adjoint_f32": ("adjoint128_f32", {"adj_local": "k_adj_local<", "adj_r": "k_adj_r<"}),
+    "particles_f32": ("case3c_256_f32", {"k1p_step": "k1p_step<", "force_move": "kp_force_move<"}),
+    "cgp_f32": ("case3cg_c_256_f32", {"fused": "k_fused_pair<", "force_move": "kp_force_move<"}),
+}
+
+
+def profile_target(P, torch, synth, name: str, steps: int, warmup: int) -> dict:
+    """Run only the kernels of one PROFILE_TARGETS entry, ``warmup`` then
+    ``steps`` steps (the command rocprofv3 counts HBM bytes on)."""
+    import numpy as np
+
+    wname, _ = PROFILE_TARGETS[name]
+    w = synth.WORKLOADS[wname]
+    t0 = time.perf_counter()
+    if name.startswith("single"):
+        rho, _ = synth.fluid_fields(w.shape, w.amp, w.seed)
+        with P.SingleFluid(w.shape, tau=w.tau[0], storage=w.storage, device=0) as lat:
+            lat.set_fields(rho.reshape(-1))
+            lat.step(warmup + steps)
+            torch.cuda.synchronize()
+    elif name.startswith("particles"):
+        rho, _ = synth.fluid_fields(w.shape, w.amp, w.seed)
+        centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+        with P.SingleFluid(w.shape, tau=w.tau[0], storage=w.storage, device=0) as lat:
+            lat.set_fields(rho.reshape(-1))
+            lat.set_particles(centres, w.radius, synth.particle_mass(w.radius))
+            lat.step(warmup + steps)
+            torch.cuda.synchronize()
+    elif name.startswith("cgp"):
+        r1, r2 = synth.colour_fields(w.shape, w.seed)
+        centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+        with P.Lattice(w.shape, tau=w.tau, storage=w.storage, rho0=w.rho0, device=0, model="colour_gradient",
+                       sigma=w.sigma, beta=w.beta) as lat:
+            lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+            lat.set_particles(centres, w.radius, synth.particle_mass(w.radius))
+            lat.step(warmup + steps)
+            torch.cuda.synchronize()
+    elif name.startswith("cg"):
+        r1, r2 = synth.colour_fields(w.shape, w.seed)
+        with P.Lattice(w.shape, tau=w.tau, storage=w.storage, device=0, model="colour_gradient", sigma=w.sigma,
+                       beta=w.beta) as lat:
+            lat.set_fields(r1.reshape(-1), r2.reshape(-1))
+            lat.step(warmup + steps)
+            torch.cuda.synchronize()
+    elif name.startswith("adjoint"):
+        from paper_2112_08264_amd import autograd as AG
+
+        a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+        spec = AG.Spec(shape=w.shape, tau=w.tau, steps=warmup + steps, every=warmup + steps, storage=w.storage)
+        ra = torch.tensor(a, device="cuda", requires_grad=True)
+        G = torch.tensor(w.G, dtype=torch.float64, requires_grad=True)
+        out = AG.final_density(ra, G, torch.tensor(b, device="cuda"), spec)
+        ((out - 1.0) ** 2).sum().backward()
+        torch.cuda.synchronize()
+    else:
+        a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+        solid = None
+        if w.spheres:
+            centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+            solid = synth.solid_mask(w.shape, centres, w.radius).reshape(-1)
+        with P.Lattice(w.shape, tau=w.tau, G=w.G, storage=w.storage, device=0) as lat:
+            lat.set_fields(a.reshape(-1), b.reshape(-1), None, solid)
+            lat.totals()
+            lat.step(warmup + steps)
+            torch.cuda.synchronize()
+    return {"profile_target": name, "workload": wname, "steps": steps, "warmup": warmup,
+            "seconds": round(time.perf_counter() - t0, 2), "np": np.__version__}
+
+
+def link_count(synth, wname: str) -> int:
+    """Links (particle node, direction with a fluid neighbour) of a particle
+    workload's initial positions: the unit of the link pass's algorithmic
+    bytes."""
+    import numpy as np
+
+    w = synth.WORKLOADS[wname]
+    centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+    solid = synth.solid_mask(w.shape, centres, w.radius).astype(bool)
+    dirs = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+            if 0 < abs(dx) + abs(dy) + abs(dz) <= 2]
+    n = 0
+    for dx, dy, dz in dirs:
+        nb = np.roll(solid, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
+        n += int(np.count_nonzero(solid & ~nb))
+    return n
+
+
+def algorithmic_bytes(synth, target: str, key: str):
+    """Algorithmic HBM bytes of one launch of a measured kernel: every value
+    the kernel must read and write once (None where that is not defined)."""
+    wname, _ = PROFILE_TARGETS[target]
+    w = synth.WORKLOADS[wname]
+    es = BYTES_PER_VALUE[w.storage]
+    if key == "fused":
+        if target.startswith("cgp"):
+            return w.nodes * (2 * 2 * 19 * es + 4)  # populations both ways and the owner word
+        return w.nodes * algorithmic_bytes_per_lup(w.storage)
+    if key == "k1_step":
+        return w.nodes * 2 * 19 * es
+    if key == "k1p_step":
+        return w.nodes * (2 * 19 * es + 4)
+    if key == "adj_local":
+        # lambda (P) 38 values pulled and 38 written, r (2) pulled, the moment record (10) read, W (6) written
+        return w.nodes * (38 + 38 + 2 + 10 + 6) * 4
+    if key == "adj_r":
+        return w.nodes * (6 + 2) * 4  # W read once, r written
+    if key == "force_move":
+        comps = 2 if target.startswith("cgp") else 1
+        # per link and component: the pushed value read, the bounce-back stored, the slot cleared, the
+        # recorded float64 density read; per link: the neighbour's owner word
+        return link_count(synth, wname) * (comps * (3 * es + 8) + 4)
+    return None
+
+
 def traffic_from_profile(kernel: str, workload: str, lups_per_launch: int):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources; else None."""
@@ -521,14 +857,17 @@ def traffic_from_profile(kernel: str, workload: str, lups_per_launch: int):
     return ent.get("bytes_per_launch")
 
 
-def write_traffic(prof_dir: str, workload: str = "spinodal256_f64", kernel_key: str = "fused") -> dict:
-    """Turn two rocprofv3 counter runs of the bench (FETCH_SIZE, then
-    WRITE_SIZE, each in its own directory pmc_<COUNTER>/) and two of
-    ``--calibrate`` (cal_<COUNTER>/) into HBM bytes per launch of the
-    dominant fused kernel, scaled by what the counters read for the 2 GiB
-    copy, and record them in profiles/traffic.json under the current kernel
-    source digest."""
+def write_traffic(prof_dir: str, target: str = "sc_f64") -> dict:
+    """Turn two rocprofv3 counter runs of ``bench.py --profile-target TARGET``
+    (FETCH_SIZE, then WRITE_SIZE, under DIR/pmc_<COUNTER>/) and two of
+    ``--calibrate`` (DIR/cal_<COUNTER>/, may be shared by several targets)
+    into HBM bytes per launch of the target's kernels, scaled by what the
+    counters read for the 2 GiB copy, and record them in
+    profiles/traffic.json under the workload and the current kernel source
+    digest."""
     import csv
+
+    import synth
 
     def rows(sub, prefix):
         path = os.path.join(prof_dir, sub, f"{prefix}_counter_collection.csv")
@@ -541,43 +880,76 @@ def write_traffic(prof_dir: str, workload: str = "spinodal256_f64", kernel_key: 
             acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return acc
 
+    wname, keys = PROFILE_TARGETS[target]
     copy_bytes = 2 << 30
-    out = {}
+    scale = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         cal = per_kernel(rows(f"cal_{counter}", "cal"))
         copy_kib = [v for k, vs in cal.items() if "copyBuffer" in k for v in vs]
-        scale = copy_bytes / (max(copy_kib) * 1024.0)
-        ker = per_kernel(rows(f"pmc_{counter}", "pmc"))
-        name = max((k for k in ker if "k_fused" in k), key=lambda k: sum(ker[k]))
-        kib = sum(ker[name]) / len(ker[name])
-        out[counter] = {"kernel": name, "kib": kib, "scale": scale, "bytes": kib * 1024.0 * scale,
-                        "dispatches": len(ker[name])}
-    w_nodes = 1
-    import synth
-    w_nodes = synth.WORKLOADS[workload].nodes
-    alg = algorithmic_bytes_per_lup(synth.WORKLOADS[workload].storage) * w_nodes
-    total = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
-    entry = {
-        "bytes_per_launch": int(round(total)),
-        "read_bytes_per_launch": int(round(out["FETCH_SIZE"]["bytes"])),
-        "write_bytes_per_launch": int(round(out["WRITE_SIZE"]["bytes"])),
-        "fetch_size_kib": out["FETCH_SIZE"]["kib"],
-        "write_size_kib": out["WRITE_SIZE"]["kib"],
-        "read_scale": out["FETCH_SIZE"]["scale"],
-        "write_scale": out["WRITE_SIZE"]["scale"],
-        "algorithmic_bytes_per_launch": alg,
-        "ratio_to_algorithmic": total / alg,
-        "kernel_symbol": out["FETCH_SIZE"]["kernel"],
-        "dispatches": [out["FETCH_SIZE"]["dispatches"], out["WRITE_SIZE"]["dispatches"]],
-        "source_digest": source_digest(),
-    }
+        scale[counter] = copy_bytes / (max(copy_kib) * 1024.0)
+    measured = {c: per_kernel(rows(os.path.join(target, f"pmc_{c}"), "pmc")) for c in ("FETCH_SIZE", "WRITE_SIZE")}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
-    data.setdefault(workload, {})[kernel_key] = entry
+    entries = {}
+    for key, sub in keys.items():
+        out = {}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            ker = measured[counter]
+            names = [k for k in ker if sub in k]
+            name = max(names, key=lambda k: sum(ker[k]))
+            kib = sum(ker[name]) / len(ker[name])
+            out[counter] = {"kernel": name, "kib": kib, "bytes": kib * 1024.0 * scale[counter],
+                            "dispatches": len(ker[name])}
+        total = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
+        alg = algorithmic_bytes(synth, target, key)
+        entry = {
+            "bytes_per_launch": int(round(total)),
+            "read_bytes_per_launch": int(round(out["FETCH_SIZE"]["bytes"])),
+            "write_bytes_per_launch": int(round(out["WRITE_SIZE"]["bytes"])),
+            "fetch_size_kib": out["FETCH_SIZE"]["kib"],
+            "write_size_kib": out["WRITE_SIZE"]["kib"],
+            "read_scale": scale["FETCH_SIZE"],
+            "write_scale": scale["WRITE_SIZE"],
+            "algorithmic_bytes_per_launch": alg,
+            "ratio_to_algorithmic": None if not alg else total / alg,
+            "kernel_symbol": out["FETCH_SIZE"]["kernel"],
+            "dispatches": [out["FETCH_SIZE"]["dispatches"], out["WRITE_SIZE"]["dispatches"]],
+            "profile_target": target,
+            "source_digest": source_digest(),
+        }
+        data.setdefault(wname, {})[key] = entry
+        entries[key] = entry
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
-    return entry
+    return entries
+
+
+def traffic_entry(workload: str, key: str):
+    """The committed counter entry of one kernel, if it was taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        ent = json.load(open(path))[workload][key]
+    except (KeyError, ValueError):
+        return None
+    return ent if ent.get("source_digest") == source_digest() else None
+
+
+def traffic_fields(workload: str, key: str, avg_ms=None) -> dict:
+    """Measured HBM bytes of a kernel next to its algorithmic bytes, and the
+    achieved fraction of 8 TB/s at its average launch time."""
+    ent = traffic_entry(workload, key)
+    if ent is None:
+        return {"traffic": None}
+    out = {"traffic": ent["bytes_per_launch"], "traffic_ratio_to_algorithmic": ent["ratio_to_algorithmic"],
+           "algorithmic_bytes_per_launch": ent["algorithmic_bytes_per_launch"]}
+    if avg_ms and ent["algorithmic_bytes_per_launch"]:
+        out["frac"] = round(ent["algorithmic_bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out["measured_bytes_frac"] = round(ent["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def main(argv=None) -> int:
@@ -590,6 +962,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16-shifted forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-adjoint-fd", action="store_true",
+                    help="skip the float64 finite-difference table of the adjoint block (about 70 forward runs)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-fluid (case 1) timing")
     ap.add_argument("--no-cg", action="store_true", help="skip the colour-gradient (case 2) timing")
     ap.add_argument("--no-particles", action="store_true", help="skip the moving-particle (case 3 fractions) timing")
@@ -599,12 +973,15 @@ def main(argv=None) -> int:
     ap.add_argument("--calibrate", action="store_true",
                     help="only time a plain device copy of 2 GiB (reference for HBM counters and bandwidth)")
     ap.add_argument("--write-traffic", metavar="DIR",
-                    help="no GPU: read rocprofv3 counter CSVs under DIR (pmc_/cal_ FETCH_SIZE, WRITE_SIZE) and "
-                         "record the fused kernel's HBM bytes per launch in profiles/traffic.json")
+                    help="no GPU: read rocprofv3 counter CSVs under DIR (cal_<COUNTER>/ and "
+                         "<target>/pmc_<COUNTER>/ for FETCH_SIZE, WRITE_SIZE) and record the HBM bytes per launch "
+                         "of the --profile-target's kernels in profiles/traffic.json")
+    ap.add_argument("--profile-target", choices=sorted(PROFILE_TARGETS),
+                    help="run only this target's kernels for --warmup + --steps steps (for rocprofv3 counters)")
     args = ap.parse_args(argv)
 
     if args.write_traffic:
-        print(json.dumps(write_traffic(args.write_traffic, args.workload)), flush=True)
+        print(json.dumps(write_traffic(args.write_traffic, args.profile_target or "sc_f64")), flush=True)
         return 0
 
     if args.gpus != 1:
@@ -624,6 +1001,9 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     if args.calibrate:
         print(json.dumps(copy_calibration(torch)), flush=True)
+        return 0
+    if args.profile_target:
+        print(json.dumps(profile_target(P, torch, synth, args.profile_target, args.steps, args.warmup)), flush=True)
         return 0
     w = synth.WORKLOADS[args.workload]
     log(f"bench: workload {w.name} {w.shape} storage {w.storage}; generating inputs")
@@ -671,7 +1051,9 @@ def main(argv=None) -> int:
             forms[st] = {"glups": round(g, 4), "ms_per_step": round(ms, 4),
                          "step_hbm_frac": round(algorithmic_bytes_per_lup(st) * g / HBM_PEAK_GBS, 4),
                          "vs_f64": round(g / glups, 3) if w.storage == "f64" else None,
-                         "nonfinite": r["nonfinite"], "kernels": r["kernels"]}
+                         "nonfinite": r["nonfinite"], "kernels": r["kernels"],
+                         **traffic_fields(f"{w.name.rsplit('_', 1)[0]}_{st}", "fused",
+                                          r["kernels"].get("fused", {}).get("avg_ms"))}
 
     accuracy = None
     if not args.no_accuracy and solid is None and w.storage == "f64":
@@ -684,8 +1066,8 @@ def main(argv=None) -> int:
 
     adjoint = None
     if not args.no_adjoint:
-        log("bench: adjoint 128^3 float32, 500 steps, checkpoint every 50")
-        adjoint = adjoint_run(P, torch, synth)
+        log("bench: adjoint 128^3, float32 and float64, 500 steps, checkpoint every 50")
+        adjoint = adjoint_run(P, torch, synth, fd=not args.no_adjoint_fd)
         log(f"bench: adjoint {adjoint}")
 
     single = None
@@ -711,6 +1093,12 @@ def main(argv=None) -> int:
         log("bench: moving particles 256^3, 0.1 / 1 / 10% of the volume")
         particles = particles_run(P, torch, synth, cpu=not args.no_cpu_baseline)
         log(f"bench: particles {particles}")
+
+    cg_particles = None
+    if not args.no_particles:
+        log("bench: moving particles in the colour-gradient fluid (case 3) 256^3, 0.1 / 1 / 10% of the volume")
+        cg_particles = cg_particles_run(P, torch, synth, cpu=not args.no_cpu_baseline)
+        log(f"bench: cg particles {cg_particles}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -745,11 +1133,13 @@ def main(argv=None) -> int:
         "forms": forms,
         "f64_one_ulp_sensitivity": None if accuracy is None else accuracy["f64_one_ulp"],
         "adjoint_forward_ratio": None if adjoint is None else adjoint["ratio"],
+        "adjoint_forward_ratio_f64": None if adjoint is None else adjoint["forms"]["f64"]["ratio"],
         "adjoint": adjoint,
         "single_fluid": single,
         "colour_gradient": cg,
         "spheres": spheres,
         "particles": particles,
+        "cg_particles": cg_particles,
         "mass_drift": main_run["mass_drift"],
         "nonfinite": main_run["nonfinite"],
         "wall_ms": round(main_run["wall_ms"], 2),

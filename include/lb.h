@@ -331,6 +331,37 @@ lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double m
                             const double* vel, const double* omega);
 lb_status lb1_get_particles(lb1_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque);
 
+/* ---- Moving particles in the colour-gradient fluid (the paper's case 3:
+ * two immiscible fluids with colloidal particles, Sec. 5; particle solver
+ * of Sec. 2, Eq. PARDYN; Sec. 3; Appendix, Eqs. UPI, LADDFLBE, FORCEPP,
+ * FORCEPARTEQ, TORQUEPARTEQ) -------------------------------------------------
+ * lb_set_particles places spheres in a context switched to
+ * LB_MODEL_COLOUR_GRADIENT, with the arguments, node ownership, mass,
+ * removal and limits of lb1_set_particles.  Per step: the colour-gradient
+ * collision at fluid nodes, where a neighbour inside a particle contributes
+ * the node's own phase field Theta to the gradient (neutral, 90 degree
+ * wetting); then, per component k, bounce-back at each link from a fluid
+ * node x into a particle node with the moving-wall term
+ *   f^k_ibar(x, t+1) = f^k*_i(x) - 2 rho^k(x) w_i (u_b . c_i) / c_s^2,
+ * u_b = v + omega x r_b at the link midpoint; the particle receives
+ * c_i (f^k*_i(x) + f^k_ibar(x, t+1)) from each component of each link,
+ * summed in float64; leap-frog; nodes a particle covers hand the momentum
+ * of both components to it, nodes it uncovers start at
+ * f^eq(rho0[k], u_b) per component and take that momentum from it.
+ * Removed particles leave fluid at rest, f^k_i = w_i rho0[k].
+ * Storage LB_F64 or LB_F32; lb_set_fields drops the particles; with
+ * particles lb_restore_state returns LB_EINVAL, lb_moments reports zeros
+ * at particle nodes and lb_totals sums the fluid only.
+ * lb_get_particles works as lb1_get_particles.
+ * Errors: LB_EINVAL (NULL ctx or pos; not the colour-gradient model; bad
+ * radius, mass, position or speed; LB_F16_SHIFTED; box larger than the
+ * lattice), LB_ESTATE (before lb_set_fields; lb_get_particles without
+ * particles), LB_ENOMEM, LB_EDEVICE.  lb_set_model back to
+ * LB_MODEL_SHAN_CHEN returns LB_EINVAL while particles are placed. */
+lb_status lb_set_particles(lb_ctx* ctx, int32_t count, double radius, double mass, const double* pos,
+                           const double* vel, const double* omega);
+lb_status lb_get_particles(lb_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque);
+
 /* ---- Conserved totals of a snapshot, without allocating -----------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -13,5 +13,5 @@ from .lb import (  # noqa: F401
     lb_set_kernel, lb_set_populations, lb_set_stream, lb_step, lb_strerror, lb_timing, lb_timing_name, lb_timing_read,
     lb_timing_slots, lb_totals, lb_snapshot_totals,
     SingleFluid, lb1_create, lb1_destroy, lb1_get_populations, lb1_moments, lb1_set_fields, lb1_set_stream, lb1_step,
-    lb1_totals, lb1_set_particles, lb1_get_particles,
+    lb1_totals, lb1_set_particles, lb1_get_particles, lb_set_particles, lb_get_particles,
 )

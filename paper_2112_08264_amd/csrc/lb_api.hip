@@ -28,9 +28,14 @@ enum KernelSlot : int {
   SLOT_ADJ_MOMENTS = 3,
   SLOT_ADJ_LOCAL = 4,
   SLOT_ADJ_R = 5,
-  SLOT_COUNT = 6
+  SLOT_PART_FORCE = 6,
+  SLOT_PART_OWNER = 7,
+  SLOT_PART_REMAP = 8,
+  SLOT_COUNT = 9
 };
-const char* const kSlotNames[SLOT_COUNT] = {"psi", "collide_push", "fused", "adj_moments", "adj_local", "adj_r"};
+const char* const kSlotNames[SLOT_COUNT] = {"psi",     "collide_push", "fused",      "adj_moments",
+                                            "adj_local", "adj_r",     "part_force", "part_owner",
+                                            "part_remap"};
 constexpr int kFusedTY = 8;   // float64 fused tiles: 32 x 8 nodes, one row per wave
 // float32 / float16-shifted fused tiles: 64 x 4 nodes, one row of 64 per wave.
 // Measured against 32 x 8: +2% (float32) and +14% (float16) at 256^3, +24%
@@ -109,6 +114,14 @@ struct lb_ctx {
   FusedTiling tiling_tall{};  // float Shan-Chen kernel without solids (64 x 8 tiles)
   bool tall = false;          // tiling_tall is used (its chunks hold >= kFloatTallMinChunk planes)
   int64_t bytes = 0;
+  // moving particles (lb_set_particles, colour-gradient model)
+  int np = 0;
+  int part_cap = 0;            // particles the buffer below holds
+  PartState ps{};
+  double* part = nullptr;      // [5][P][3]: pos, vel, omg, force, torque
+  int* owner[2] = {nullptr, nullptr};
+  int ocur = 0;
+  double* rho_buf = nullptr;   // [2][N] densities recorded near particles
 };
 
 namespace {
@@ -161,9 +174,10 @@ void free_all(lb_ctx* ctx) {
   ctx->launches.clear();
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   ctx->event_pool.clear();
-  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi,    ctx->mask,   ctx->partial,     ctx->result,
-                  ctx->flag,    ctx->plane,   ctx->lam[0], ctx->lam[1], ctx->amom,        ctx->wbuf,
-                  ctx->rbuf,    ctx->adj_partial, ctx->adj_dG};
+  void* bufs[] = {ctx->grid[0], ctx->grid[1], ctx->psi,         ctx->mask,   ctx->partial,  ctx->result,
+                  ctx->flag,    ctx->plane,   ctx->lam[0],      ctx->lam[1], ctx->amom,     ctx->wbuf,
+                  ctx->rbuf,    ctx->adj_partial, ctx->adj_dG,  ctx->part,   ctx->owner[0], ctx->owner[1],
+                  ctx->rho_buf};
   for (void* b : bufs)
     if (b != nullptr) (void)hipFree(b);
 }
@@ -218,7 +232,8 @@ lb_status fold_timing(lb_ctx* ctx) {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-const uint8_t* mask_or_null(const lb_ctx* ctx) { return ctx->has_solid ? ctx->mask : nullptr; }
+// mask of solid nodes (fixed solids or particles), or nullptr
+const uint8_t* mask_or_null(const lb_ctx* ctx) { return (ctx->has_solid || ctx->np > 0) ? ctx->mask : nullptr; }
 
 // ---------------------------------------------------------------------------
 // Typed implementations
@@ -432,8 +447,63 @@ bool use_fused(const lb_ctx* ctx) {
   return (ctx->kernel == LB_KERNEL_FUSED || ctx->kernel == LB_KERNEL_FUSED_STAGED) && fused_fits(ctx);
 }
 
+// Colour-gradient step with moving particles, per step: the pair kernel
+// with the particle coupling (blind push, densities near particles), the
+// link pass with forces and leap-frog, the owner map of the new positions,
+// covering and uncovering.  Structure-of-arrays layout throughout.
+template <int ST>
+lb_status particle_step_impl(lb_ctx* ctx, int n) {
+  if constexpr (ST == ST_F16S) {
+    return LB_EINVAL;  // lb_set_particles admits float64 and float32 storage only
+  } else {
+    using store = typename StorageTraits<ST>::store_t;
+    lb_status st = set_layout(ctx, false);
+    if (st != LB_OK) return st;
+    for (int s = 0; s < n; ++s) {
+      const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
+      store* fout = static_cast<store*>(ctx->grid[ctx->cur ^ 1]);
+      const int* own = ctx->owner[ctx->ocur];
+      int* own_new = ctx->owner[ctx->ocur ^ 1];
+      const PartFluid pf{own, ctx->rho_buf};
+      st = launch(ctx, SLOT_FUSED, [&] {
+        if constexpr (ST == ST_F64) {
+          const FusedTiling t = ctx->tiling;
+          k_fused_pair<ST, true, kFusedTY, false, false, kFusedTX, kModelCG, false, true>
+              <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr,
+                                                                        pf);
+        } else {
+          const FusedTiling t = ctx->tiling_cg;
+          k_fused_pair<ST, true, kFloatTY, false, false, kFloatTX, kModelCG, false, true>
+              <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                                   nullptr, pf);
+        }
+      });
+      if (st != LB_OK) return st;
+      st = launch(ctx, SLOT_PART_FORCE, [&] {
+        kp_force_move<ST, 2><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g,
+                                                                        ctx->c);
+      });
+      if (st != LB_OK) return st;
+      st = launch(ctx, SLOT_PART_OWNER, [&] {
+        kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(own_new, ctx->g.N);
+        kp_owner_scatter<<<ctx->np, kBlock, 0, ctx->stream>>>(own_new, ctx->ps, ctx->g);
+      });
+      if (st != LB_OK) return st;
+      st = launch(ctx, SLOT_PART_REMAP, [&] {
+        kp_remap<ST, 2><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps, ctx->g,
+                                                                   ctx->c);
+      });
+      if (st != LB_OK) return st;
+      ctx->cur ^= 1;
+      ctx->ocur ^= 1;
+    }
+    return LB_OK;
+  }
+}
+
 template <int ST>
 lb_status step_impl(lb_ctx* ctx, int n) {
+  if (ctx->np > 0) return particle_step_impl<ST>(ctx, n);
   if (use_fused(ctx)) return fused_step_impl<ST>(ctx, n);
   if (ctx->model != LB_MODEL_SHAN_CHEN) return LB_EINVAL;  // the colour-gradient step is fused only
   {
@@ -513,7 +583,7 @@ lb_status moments_impl(lb_ctx* ctx, double* ra, double* rb, double* u) {
     c.G = 0.0;
     c.Gf = 0.0f;
   }
-  if (ctx->has_solid) {
+  if (mask_or_null(ctx) != nullptr) {
     k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, c);
     k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, c);
   } else {
@@ -756,6 +826,118 @@ void free1(lb1_ctx* ctx) {
   for (void* b : bufs)
     if (b != nullptr) (void)hipFree(b);
 }
+
+// Particle state of either context to host arrays (each may be NULL).
+template <class Ctx>
+lb_status get_particles_common(Ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque) {
+  if (ctx->np == 0) return LB_ESTATE;
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t P = static_cast<size_t>(ctx->np);
+  double* outs[5] = {pos, vel, omega, force, torque};
+  const double* srcs[5] = {ctx->ps.pos, ctx->ps.vel, ctx->ps.omg, ctx->ps.force, ctx->ps.torque};
+  for (int k = 0; k < 5; ++k)
+    if (outs[k] != nullptr)
+      LB_HIP(hipMemcpyAsync(outs[k], srcs[k], sizeof(double) * 3 * P, hipMemcpyDeviceToHost, ctx->stream));
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  return LB_OK;
+}
+
+// Particles of either context, after the caller has checked what its
+// context admits: NC = 1 for the single fluid, 2 for the colour-gradient
+// pair (whose grid must be in the structure-of-arrays layout).  `alloc`
+// allocates device memory owned by the context.
+template <int NC, class Ctx, class Alloc>
+lb_status set_particles_common(Ctx* ctx, int32_t count, double radius, double mass, const double* pos,
+                               const double* vel, const double* omega, Alloc&& alloc) {
+  auto release = [&]() -> lb_status {  // the current particles' nodes turn to fluid at rest
+    if (ctx->np == 0) return LB_OK;
+    DeviceGuard dg(ctx->p.device);
+    if (!dg.ok) return LB_EDEVICE;
+    lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+      constexpr int ST = decltype(tag)::value;
+      kp_release<ST, NC><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+          static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->mask, ctx->p.rho0[0],
+          ctx->p.rho0[1], ctx->g, ctx->c);
+      return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+    });
+    if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
+    if (st == LB_OK) ctx->np = 0;
+    return st;
+  };
+  if (count == 0) return release();
+  if (!is_finite(radius) || !(radius > 0.0) || std::isnan(mass) || !(mass > 0.0)) return LB_EINVAL;
+  const int box = static_cast<int>(std::floor(2.0 * radius)) + 4;
+  if (box > ctx->g.nx || box > ctx->g.ny || box > ctx->g.nz) return LB_EINVAL;  // a particle's box must fit the lattice
+  const double L[3] = {double(ctx->g.nx), double(ctx->g.ny), double(ctx->g.nz)};
+  const size_t P = static_cast<size_t>(count);
+  std::vector<double> host(15 * P, 0.0);
+  for (size_t q = 0; q < P; ++q)
+    for (int a = 0; a < 3; ++a) {
+      const double r = pos[3 * q + a];
+      const double v = vel ? vel[3 * q + a] : 0.0;
+      const double w = omega ? omega[3 * q + a] : 0.0;
+      if (!is_finite(r) || r < 0.0 || r >= L[a]) return LB_EINVAL;
+      if (!is_finite(v) || !(std::fabs(v) < 0.5) || !is_finite(w)) return LB_EINVAL;  // under half a node per step
+      host[3 * q + a] = r;
+      host[3 * P + 3 * q + a] = v;
+      host[6 * P + 3 * q + a] = w;
+    }
+  {
+    lb_status st = release();
+    if (st != LB_OK) return st;
+  }
+  DeviceGuard dg(ctx->p.device);
+  if (!dg.ok) return LB_EDEVICE;
+  const size_t N = static_cast<size_t>(ctx->g.N);
+  if (ctx->part != nullptr && ctx->part_cap < count) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->part);
+    ctx->part = nullptr;
+    ctx->part_cap = 0;
+  }
+  if (ctx->part == nullptr) {
+    if (alloc(reinterpret_cast<void**>(&ctx->part), sizeof(double) * 15 * P) != LB_OK) return LB_ENOMEM;
+    ctx->part_cap = count;
+  }
+  for (int b = 0; b < 2; ++b)
+    if (ctx->owner[b] == nullptr && alloc(reinterpret_cast<void**>(&ctx->owner[b]), sizeof(int) * N) != LB_OK)
+      return LB_ENOMEM;
+  if (ctx->rho_buf == nullptr && alloc(reinterpret_cast<void**>(&ctx->rho_buf), sizeof(double) * NC * N) != LB_OK)
+    return LB_ENOMEM;
+  if (ctx->mask == nullptr && alloc(reinterpret_cast<void**>(&ctx->mask), N) != LB_OK) return LB_ENOMEM;
+  PartState& ps = ctx->ps;
+  ps.pos = ctx->part;
+  ps.vel = ctx->part + 3 * P;
+  ps.omg = ctx->part + 6 * P;
+  ps.force = ctx->part + 9 * P;
+  ps.torque = ctx->part + 12 * P;
+  ps.count = count;
+  ps.box = box;
+  ps.radius = radius;
+  ps.r2 = radius * radius;
+  ps.near2 = (radius + 1.5) * (radius + 1.5);
+  ps.inner2 = radius > 1.5 ? (radius - 1.5) * (radius - 1.5) : -1.0;
+  ps.mass = mass;
+  ps.inertia = 0.4 * mass * radius * radius;
+  ps.rho0[0] = ctx->p.rho0[0];
+  ps.rho0[1] = NC == 2 ? ctx->p.rho0[1] : ctx->p.rho0[0];
+  LB_HIP(hipMemcpyAsync(ctx->part, host.data(), sizeof(double) * 15 * P, hipMemcpyHostToDevice, ctx->stream));
+  ctx->ocur = 0;
+  kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ctx->owner[0], ctx->g.N);
+  kp_owner_scatter<<<count, kBlock, 0, ctx->stream>>>(ctx->owner[0], ps, ctx->g);
+  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
+    constexpr int ST = decltype(tag)::value;
+    kp_apply_owner<ST, NC><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->owner[0], ctx->mask, ctx->g);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+  });
+  if (st != LB_OK) return st;
+  LB_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->np = count;
+  return LB_OK;
+}
+
 
 }  // namespace
 
@@ -1109,6 +1291,7 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b, c
   } else {
     ctx->has_solid = false;
   }
+  ctx->np = 0;  // new fields drop the particles
   lb_status st = by_storage(ctx, [&](auto tag) { return init_impl<decltype(tag)::value>(ctx, dra, drb, du); });
   if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
   release();
@@ -1257,6 +1440,7 @@ lb_status lb_set_model(lb_ctx* ctx, int32_t model, double sigma, double beta) {
   if (model != LB_MODEL_SHAN_CHEN && model != LB_MODEL_COLOUR_GRADIENT) return LB_EINVAL;
   if (!is_finite(sigma) || !is_finite(beta) || sigma < 0.0 || beta < 0.0) return LB_EINVAL;
   if (model == LB_MODEL_COLOUR_GRADIENT && (ctx->p.storage == LB_F16_SHIFTED || ctx->has_solid)) return LB_EINVAL;
+  if (model != LB_MODEL_COLOUR_GRADIENT && ctx->np > 0) return LB_EINVAL;  // particles live in the colour-gradient fluid
   StepCoeffs& c = ctx->c;
   for (int k = 0; k < 2; ++k) {
     c.cg_inv_nu[k] = 1.0 / ((ctx->p.tau[k] - 0.5) / 3.0);
@@ -1311,6 +1495,7 @@ lb_status lb_save_state(lb_ctx* ctx, void* dst, int on_device) {
 
 lb_status lb_restore_state(lb_ctx* ctx, const void* src, int on_device) {
   if (ctx == nullptr || src == nullptr) return LB_EINVAL;
+  if (ctx->np > 0) return LB_EINVAL;  // a snapshot holds no particle state
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
   if (!ctx->has_state) LB_HIP(hipMemsetAsync(ctx->grid[ctx->cur ^ 1], 0, ctx->grid_bytes, ctx->stream));
@@ -1770,106 +1955,33 @@ lb_status lb1_set_particles(lb1_ctx* ctx, int32_t count, double radius, double m
   if (ctx == nullptr || count < 0) return LB_EINVAL;
   if (!ctx->has_state) return LB_ESTATE;
   if (count > 0 && (pos == nullptr || ctx->has_solid || ctx->p.storage == LB_F16_SHIFTED)) return LB_EINVAL;
-  auto release = [&]() -> lb_status {  // the current particles' nodes turn to fluid at rest
-    if (ctx->np == 0) return LB_OK;
-    DeviceGuard dg(ctx->p.device);
-    if (!dg.ok) return LB_EDEVICE;
-    lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
-      constexpr int ST = decltype(tag)::value;
-      kp_release<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
-          static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->mask, ctx->p.rho0[0], ctx->g,
-          ctx->c);
-      return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
-    });
-    if (st == LB_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = LB_EDEVICE;
-    if (st == LB_OK) ctx->np = 0;
-    return st;
-  };
-  if (count == 0) return release();
-  if (!is_finite(radius) || !(radius > 0.0) || std::isnan(mass) || !(mass > 0.0)) return LB_EINVAL;
-  const int box = static_cast<int>(std::floor(2.0 * radius)) + 4;
-  if (box > ctx->g.nx || box > ctx->g.ny || box > ctx->g.nz) return LB_EINVAL;  // a particle's box must fit the lattice
-  const double L[3] = {double(ctx->g.nx), double(ctx->g.ny), double(ctx->g.nz)};
-  const size_t P = static_cast<size_t>(count);
-  std::vector<double> host(15 * P, 0.0);
-  for (size_t q = 0; q < P; ++q)
-    for (int a = 0; a < 3; ++a) {
-      const double r = pos[3 * q + a];
-      const double v = vel ? vel[3 * q + a] : 0.0;
-      const double w = omega ? omega[3 * q + a] : 0.0;
-      if (!is_finite(r) || r < 0.0 || r >= L[a]) return LB_EINVAL;
-      if (!is_finite(v) || !(std::fabs(v) < 0.5) || !is_finite(w)) return LB_EINVAL;  // under half a node per step
-      host[3 * q + a] = r;
-      host[3 * P + 3 * q + a] = v;
-      host[6 * P + 3 * q + a] = w;
-    }
-  {
-    lb_status st = release();
-    if (st != LB_OK) return st;
-  }
-  DeviceGuard dg(ctx->p.device);
-  if (!dg.ok) return LB_EDEVICE;
-  const size_t N = static_cast<size_t>(ctx->g.N);
-  if (ctx->part != nullptr && ctx->part_cap < count) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(ctx->part);
-    ctx->part = nullptr;
-    ctx->part_cap = 0;
-  }
-  if (ctx->part == nullptr) {
-    if (alloc1(reinterpret_cast<void**>(&ctx->part), sizeof(double) * 15 * P) != LB_OK) return LB_ENOMEM;
-    ctx->part_cap = count;
-  }
-  for (int b = 0; b < 2; ++b)
-    if (ctx->owner[b] == nullptr && alloc1(reinterpret_cast<void**>(&ctx->owner[b]), sizeof(int) * N) != LB_OK)
-      return LB_ENOMEM;
-  if (ctx->rho_buf == nullptr && alloc1(reinterpret_cast<void**>(&ctx->rho_buf), sizeof(double) * N) != LB_OK)
-    return LB_ENOMEM;
-  if (ctx->mask == nullptr && alloc1(reinterpret_cast<void**>(&ctx->mask), N) != LB_OK) return LB_ENOMEM;
-  PartState& ps = ctx->ps;
-  ps.pos = ctx->part;
-  ps.vel = ctx->part + 3 * P;
-  ps.omg = ctx->part + 6 * P;
-  ps.force = ctx->part + 9 * P;
-  ps.torque = ctx->part + 12 * P;
-  ps.count = count;
-  ps.box = box;
-  ps.radius = radius;
-  ps.r2 = radius * radius;
-  ps.near2 = (radius + 1.5) * (radius + 1.5);
-  ps.inner2 = radius > 1.5 ? (radius - 1.5) * (radius - 1.5) : -1.0;
-  ps.mass = mass;
-  ps.inertia = 0.4 * mass * radius * radius;
-  ps.rho0 = ctx->p.rho0[0];
-  LB_HIP(hipMemcpyAsync(ctx->part, host.data(), sizeof(double) * 15 * P, hipMemcpyHostToDevice, ctx->stream));
-  ctx->ocur = 0;
-  kp_owner_fill<<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(ctx->owner[0], ctx->g.N);
-  kp_owner_scatter<<<count, kBlock, 0, ctx->stream>>>(ctx->owner[0], ps, ctx->g);
-  lb_status st = by_storage_id(ctx->p.storage, [&](auto tag) {
-    constexpr int ST = decltype(tag)::value;
-    kp_apply_owner<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
-        static_cast<typename StorageTraits<ST>::store_t*>(ctx->grid[ctx->cur]), ctx->owner[0], ctx->mask, ctx->g);
-    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
-  });
-  if (st != LB_OK) return st;
-  LB_HIP(hipStreamSynchronize(ctx->stream));
-  ctx->np = count;
-  return LB_OK;
+  return set_particles_common<1>(ctx, count, radius, mass, pos, vel, omega,
+                                 [](void** ptr, size_t bytes) { return alloc1(ptr, bytes); });
 }
 
 lb_status lb1_get_particles(lb1_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque) {
   if (ctx == nullptr) return LB_EINVAL;
-  if (ctx->np == 0) return LB_ESTATE;
+  return get_particles_common(ctx, pos, vel, omega, force, torque);
+}
+
+lb_status lb_set_particles(lb_ctx* ctx, int32_t count, double radius, double mass, const double* pos,
+                           const double* vel, const double* omega) {
+  if (ctx == nullptr || count < 0) return LB_EINVAL;
+  if (!ctx->has_state) return LB_ESTATE;
+  if (count > 0 && (pos == nullptr || ctx->model != LB_MODEL_COLOUR_GRADIENT || ctx->has_solid ||
+                    ctx->p.storage == LB_F16_SHIFTED))
+    return LB_EINVAL;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  const size_t P = static_cast<size_t>(ctx->np);
-  double* outs[5] = {pos, vel, omega, force, torque};
-  const double* srcs[5] = {ctx->ps.pos, ctx->ps.vel, ctx->ps.omg, ctx->ps.force, ctx->ps.torque};
-  for (int k = 0; k < 5; ++k)
-    if (outs[k] != nullptr)
-      LB_HIP(hipMemcpyAsync(outs[k], srcs[k], sizeof(double) * 3 * P, hipMemcpyDeviceToHost, ctx->stream));
-  LB_HIP(hipStreamSynchronize(ctx->stream));
-  return LB_OK;
+  const lb_status st = set_layout(ctx, false);  // the particle kernels address the structure of arrays
+  if (st != LB_OK) return st;
+  return set_particles_common<2>(ctx, count, radius, mass, pos, vel, omega,
+                                 [ctx](void** ptr, size_t bytes) { return dev_alloc(ctx, ptr, bytes); });
+}
+
+lb_status lb_get_particles(lb_ctx* ctx, double* pos, double* vel, double* omega, double* force, double* torque) {
+  if (ctx == nullptr) return LB_EINVAL;
+  return get_particles_common(ctx, pos, vel, omega, force, torque);
 }
 
 }  // extern "C"

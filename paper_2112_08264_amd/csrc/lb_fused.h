@@ -392,6 +392,23 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   }
 }
 
+// Owner map of moving particles: the particle index at solid nodes; at fluid
+// nodes kOwnerFluid, or kOwnerNear within R + 1.5 of a centre (every fluid
+// end of a link lies within R + sqrt 2), where the fluid step records the
+// density for the particles' link pass.
+constexpr int kOwnerFluid = 0x7fffffff;
+constexpr int kOwnerNear = 0x7ffffffe;  // fluid, possibly next to a particle
+
+__device__ __forceinline__ bool owner_fluid(int o) { return o >= kOwnerNear; }
+
+// Particle coupling of the colour-gradient pair kernel (PART): the owner map
+// of the current positions and the float64 densities [2][N] that fluid nodes
+// near a particle record for the link pass.
+struct PartFluid {
+  const int* owner;
+  double* rho;
+};
+
 // ---------------------------------------------------------------------------
 // Component-pair variant (float64 Shan-Chen; every colour-gradient step).
 // Each wave holds 32 nodes of one tile row for both components: lanes 0..31
@@ -423,13 +440,23 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
 //
 // TILED: the populations are in the tile-major layout (64 x 4 tiles, no
 // solids, either model); only the addressing differs.
+//
+// PART (colour gradient with moving particles, structure of arrays,
+// unstaged): the solid nodes are those the owner map gives to a particle.
+// Neutral wetting: in the phase-field stencil of a fluid node, a neighbour
+// inside a particle contributes the node's own Theta.  Streaming is blind:
+// every fluid node pushes its 19 post-collision populations to x + c_i and
+// every solid node pushes zeros, so that the particles' link pass finds the
+// population sent into a particle waiting in the particle node's slot (and
+// the zero it replaces in the fluid node's).  Fluid nodes near a particle
+// record rho_A and rho_B for that pass.
 template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC,
-          bool TILED = false>
+          bool TILED = false, bool PART = false>
 __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
                                                             store_t<ST>* __restrict__ fout,
                                                             const uint8_t* __restrict__ mask, Geometry g,
                                                             StepCoeffs c, FusedTiling t,
-                                                            real_t<ST>* __restrict__ rec) {
+                                                            real_t<ST>* __restrict__ rec, PartFluid pf = {}) {
   using real = real_t<ST>;
   constexpr int WPR = TX / 32;  // waves per tile row
   constexpr int NW = TY * WPR;  // waves per workgroup
@@ -441,11 +468,15 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   // With solids the staged variant needs more than the 256 registers two
   // waves per SIMD allow and spills; the unstaged kernel is faster there.
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
-  static_assert(MODEL == kModelSC || (!SOLID && !RECORD), "the colour-gradient step has no solids and no adjoint record");
+  static_assert(MODEL == kModelSC || (!RECORD && (!SOLID || PART)),
+                "the colour-gradient step has no adjoint record, and solids only as particles");
+  static_assert(!PART || (SOLID && MODEL == kModelCG && !STAGED && !TILED && sizeof(store_t<ST>) >= 4),
+                "particles: colour gradient, unstaged, structure of arrays, float32 or float64 storage");
   static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && !SOLID && !RECORD),
                 "the tile-major layout serves the 64-wide step without solids or record");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
+  // bit 0: solid; 2: fluid near a particle (PART)
   __shared__ uint8_t ring_solid[SOLID ? 3 : 1][SOLID ? RY : 1][SOLID ? RX : 1];
   constexpr int KI = 2 * Q;                      // population planes of both components
   constexpr int ST_ROWS = KI * RY * TX;          // [ki][row -1 .. TY][x] block
@@ -561,7 +592,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       ring[s][kk][y][x] = (SOLID && solid) ? real(0) : pseudopotential(rho, coef_ref<real>(c));
     } else {
       const real o = __shfl_xor(rho, pm, 64);
-      if (kk == 0) ring[s][0][y][x] = (rho - o) / (rho + o);
+      if (kk == 0) ring[s][0][y][x] = (SOLID && solid) ? real(0) : (rho - o) / (rho + o);
     }
   };
 
@@ -577,16 +608,23 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     const long long zoff = plane_n * z;
     {
       const long long n = row + zoff;
-      bool solid = false;
-      if constexpr (SOLID) solid = mask[n] != 0;
+      bool solid = false, near = false;
+      if constexpr (PART) {
+        const int o = pf.owner[n];
+        solid = !owner_fluid(o);
+        near = o == kOwnerNear;
+      } else if constexpr (SOLID) {
+        solid = mask[n] != 0;
+      }
       const real rho = TILED ? rho_tiled(gx, gy, z, k, keep) : rho_of(n, kplane, k, keep);
       ring_put(s, k, ly + 1, lx + 1, rho, solid, 32);
-      if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid;
+      if constexpr (SOLID) if (k == 0) ring_solid[s][ly + 1][lx + 1] = solid ? 1 : (near ? 2 : 0);
     }
     if (has_halo) {
       const long long n = hrow + zoff;
       bool solid = false;
-      if constexpr (SOLID) solid = mask[n] != 0;
+      if constexpr (PART) solid = !owner_fluid(pf.owner[n]);
+      else if constexpr (SOLID) solid = mask[n] != 0;
       real tmp[Q];
       const real rho = TILED ? rho_tiled(hgx, hgy, z, hk, tmp) : rho_of(n, hkplane, hk, tmp);
       ring_put(s, hk, hy + 1, hx + 1, rho, solid, 1);
@@ -617,7 +655,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     }
 
     bool here_solid = false;
-    if constexpr (SOLID) here_solid = ring_solid[s0][ly + 1][lx + 1] != 0;
+    if constexpr (SOLID) here_solid = (ring_solid[s0][ly + 1][lx + 1] & 1) != 0;
     const real rho_k = density<real>(cur);
     real m_k[3] = {lattice_sum<0, 0, real>(cur), lattice_sum<1, 0, real>(cur), lattice_sum<2, 0, real>(cur)};
     const real rho_o = __shfl_xor(rho_k, 32, 64);
@@ -633,13 +671,18 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
       up[a] = (omA * mA + omB * mB) / den;
     }
     // S = sum_i w_i q(x + c_i) c_i, q = psi of the other component
-    // (Shan-Chen) or the phase field (colour gradient)
+    // (Shan-Chen) or the phase field (colour gradient; with particles a
+    // neighbour inside one gives this node's own phase field)
     constexpr bool SC = MODEL == kModelSC;
     real S[3] = {real(0), real(0), real(0)};
+    [[maybe_unused]] const real theta_here = ring[s0][0][ly + 1][lx + 1];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-      const real tt = weight<real>(i) * ring[si][SC ? 1 - k : 0][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      real q = ring[si][SC ? 1 - k : 0][ly + 1 + CY[i]][lx + 1 + CX[i]];
+      if constexpr (PART)
+        if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]] & 1) q = theta_here;
+      const real tt = weight<real>(i) * q;
       if (CX[i] == 1) S[0] = S[0] + tt;
       if (CX[i] == -1) S[0] = S[0] - tt;
       if (CY[i] == 1) S[1] = S[1] + tt;
@@ -655,6 +698,9 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     const real vz = up[2] - ak * S[2];
     const real vv = (vx * vx + vy * vy) + vz * vz;
     const real t15 = real(1.5) * vv;
+    if constexpr (PART) {
+      if (active && ring_solid[s0][ly + 1][lx + 1] == 2) pf.rho[(long long)k * g.N + row + plane_n * z] = double(rho_k);
+    }
     if constexpr (RECORD) {
       if (active) {
         const long long node = row + plane_n * z;
@@ -703,7 +749,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
           if constexpr (SOLID) {
             if (i != 0) {
               const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-              if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]]) bounced |= 1u << i;
+              if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]] & 1) bounced |= 1u << i;
             }
           }
         }
@@ -753,6 +799,14 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
         for (int i = 0; i < Q; ++i) cur[i] = fs[i];
       } else {
         push(fs, bounced);
+      }
+    }
+    if constexpr (PART) {
+      if (active && here_solid) {
+        real zero[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) zero[i] = real(0);
+        push(zero, 0u);
       }
     }
     if constexpr (STAGED) {

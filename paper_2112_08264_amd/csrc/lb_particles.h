@@ -1,11 +1,13 @@
-// Moving rigid spheres in the single-fluid step: the paper's particle solver
-// (Sec. 2, Eq. PARDYN with leap-frog; Sec. 3 step order; Appendix, Eqs. UPI,
-// LADDFLBE, FORCEPP, FORCEPARTEQ, TORQUEPARTEQ), HIP kernels.
+// Moving rigid spheres in the single-fluid step and in the two-component
+// colour-gradient step: the paper's particle solver (Sec. 2, Eq. PARDYN with
+// leap-frog; Sec. 3 step order; Appendix, Eqs. UPI, LADDFLBE, FORCEPP,
+// FORCEPARTEQ, TORQUEPARTEQ), HIP kernels.
 //
 // One step, t -> t + 1 (each line one launch):
 //   k1p_step         collide fluid nodes and push every population, solid
 //                    nodes push zeros; fluid nodes near a particle record
-//                    their density
+//                    their density (two components: k_fused_pair with PART,
+//                    which records rho_A and rho_B)
 //   kp_force_move    one workgroup per particle: bounce-back at its links with
 //                    the moving-wall correction W_i = 2 rho w_i (u_b . c_i) / c_s^2,
 //                    u_b = v + omega x r_b; force and torque summed over the
@@ -20,6 +22,13 @@
 // Particle arithmetic (positions, surface velocities, W_i, forces) is
 // float64 whatever the storage: the paper accumulates particle forces in
 // double precision because the link terms cancel strongly.
+//
+// Two components (NC = 2): each component bounces back with its own
+// density in the wall term, W^k_i = 2 rho^k w_i (u_b . c_i) / c_s^2, so that
+// the pair carries the single-fluid term of the mixture density, and the
+// particle receives the momentum of both components' links; covered nodes
+// hand over both components, uncovered nodes start each component at
+// f^eq(rho0_k, u_b).
 //
 // Fixed summation order of a particle's link and covering sums, so that
 // they are reproducible bit for bit.  The particle's box has S nodes per axis
@@ -39,12 +48,8 @@
 
 namespace lbd {
 
-constexpr int kOwnerFluid = 0x7fffffff;
-constexpr int kOwnerNear = 0x7ffffffe;  // fluid, possibly next to a particle
 constexpr int kPartThreads = 256;
 constexpr int kLinkChunk = 6;  // directions whose link loads are in flight together (divides 18)
-
-__device__ __forceinline__ bool owner_fluid(int o) { return o >= kOwnerNear; }
 
 struct PartState {
   double* pos;     // [P][3], in [0, L)
@@ -54,7 +59,8 @@ struct PartState {
   double* torque;  // [P][3]
   int count;
   int box;         // S = floor(2R) + 4
-  double radius, r2, near2, inner2, mass, inertia, rho0;  // R^2, (R + 1.5)^2, (R - 1.5)^2 or -1
+  double radius, r2, near2, inner2, mass, inertia;  // R^2, (R + 1.5)^2, (R - 1.5)^2 or -1
+  double rho0[2];  // density of each component at nodes the particles uncover
 };
 
 // Periodic wrap of any coordinate (a box of a particle whose state has gone
@@ -205,7 +211,11 @@ __device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6
 // are queued in LDS in box order, 256 at a time, so that every thread works
 // on one (a seventh or so of the box); thread l takes queue entries
 // l, l + 256, ..., which is the fixed order above.
-template <int ST>
+//
+// NC components: the populations of component k are planes k Q .. k Q + 18,
+// its recorded densities rho_buf[k N ..]; each link is handled per
+// component, component 0 first.
+template <int ST, int NC = 1>
 __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __restrict__ fnew,
                                                               const int* __restrict__ owner,
                                                               const double* __restrict__ rho_buf, PartState ps,
@@ -237,44 +247,52 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
 #pragma unroll
     for (int i0 = 1; i0 < Q; i0 += kLinkChunk) {
       int nf[kLinkChunk], of[kLinkChunk];
-      real pushed[kLinkChunk];
-      double rh[kLinkChunk];
+      bool outside[kLinkChunk];
 #pragma unroll
       for (int k = 0; k < kLinkChunk; ++k) {
         const int i = i0 + k;
         const double ex = double(cc[0] - CX[i]) - q.r[0], ey = double(cc[1] - CY[i]) - q.r[1],
                      ez = double(cc[2] - CZ[i]) - q.r[2];
-        const bool outside = (ex * ex + ey * ey) + ez * ez > ps.r2;
+        outside[k] = (ex * ex + ey * ey) + ez * ez > ps.r2;
         nf[k] = wrap_step(xs - CX[i], g.nx) + g.nx * (wrap_step(ys - CY[i], g.ny) + g.ny * wrap_step(zs - CZ[i], g.nz));
-        of[k] = p;  // solid
-        pushed[k] = real(0);
-        rh[k] = 0.0;
-        if (outside) {
-          of[k] = owner[nf[k]];
-          pushed[k] = decode<ST>(fnew[(long long)i * g.Npad + n], c.shift[0][i]);
-          rh[k] = rho_buf[nf[k]];
-        }
+        of[k] = outside[k] ? owner[nf[k]] : p;  // inside this particle: solid
       }
 #pragma unroll
-      for (int k = 0; k < kLinkChunk; ++k) {
-        const int i = i0 + k;
-        if (!owner_fluid(of[k])) continue;
-        const int xf = wrap_step(xs - CX[i], g.nx), yf = wrap_step(ys - CY[i], g.ny), zf = wrap_step(zs - CZ[i], g.nz);
-        double rb[3];
-        const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
-        const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[0][i]);  // w_opp(i) = w_i
-        fnew[(long long)OPP[i] * g.Npad + nf[k]] = back;
-        fnew[(long long)i * g.Npad + n] = store_t<ST>(0);
-        const double gv = static_cast<double>(decode<ST>(back, c.shift[0][i]));
-        const double t = (gv + gv) + W;
-        const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
-                             CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
-        acc[0] = acc[0] + F[0];
-        acc[1] = acc[1] + F[1];
-        acc[2] = acc[2] + F[2];
-        acc[3] = acc[3] + (rb[1] * F[2] - rb[2] * F[1]);
-        acc[4] = acc[4] + (rb[2] * F[0] - rb[0] * F[2]);
-        acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
+      for (int kc = 0; kc < NC; ++kc) {
+        const long long kp = (long long)(kc * Q) * g.Npad;
+        real pushed[kLinkChunk];
+        double rh[kLinkChunk];
+#pragma unroll
+        for (int k = 0; k < kLinkChunk; ++k) {
+          const int i = i0 + k;
+          pushed[k] = real(0);
+          rh[k] = 0.0;
+          if (outside[k]) {
+            pushed[k] = decode<ST>(fnew[kp + (long long)i * g.Npad + n], c.shift[kc][i]);
+            rh[k] = rho_buf[(long long)kc * g.N + nf[k]];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kLinkChunk; ++k) {
+          const int i = i0 + k;
+          if (!owner_fluid(of[k])) continue;
+          const int xf = wrap_step(xs - CX[i], g.nx), yf = wrap_step(ys - CY[i], g.ny), zf = wrap_step(zs - CZ[i], g.nz);
+          double rb[3];
+          const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
+          const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[kc][i]);  // w_opp(i) = w_i
+          fnew[kp + (long long)OPP[i] * g.Npad + nf[k]] = back;
+          fnew[kp + (long long)i * g.Npad + n] = store_t<ST>(0);
+          const double gv = static_cast<double>(decode<ST>(back, c.shift[kc][i]));
+          const double t = (gv + gv) + W;
+          const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
+                               CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
+          acc[0] = acc[0] + F[0];
+          acc[1] = acc[1] + F[1];
+          acc[2] = acc[2] + F[2];
+          acc[3] = acc[3] + (rb[1] * F[2] - rb[2] * F[1]);
+          acc[4] = acc[4] + (rb[2] * F[0] - rb[0] * F[2]);
+          acc[5] = acc[5] + (rb[0] * F[1] - rb[1] * F[0]);
+        }
       }
     }
   };
@@ -353,7 +371,8 @@ __global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ own
 }
 
 // Covering and uncovering after the move; mask follows the new owner map.
-template <int ST>
+// NC components, each handled in turn at a node, component 0 first.
+template <int ST, int NC = 1>
 __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict__ f, const int* __restrict__ owner_old,
                                                          const int* __restrict__ owner_new, uint8_t* __restrict__ mask,
                                                          PartState ps, Geometry g, StepCoeffs c) {
@@ -372,44 +391,47 @@ __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict
     const bool uncovered = owner_old[n] == p && owner_fluid(owner_new[n]);
     if (!covered && !uncovered) continue;
     const double d[3] = {double(cc[0]) - r[0], double(cc[1]) - r[1], double(cc[2]) - r[2]};
-    real vals[Q];
-    double sign;
-    if (covered) {
+    mask[n] = covered ? 1 : 0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        vals[i] = decode<ST>(f[(long long)i * g.Npad + n], c.shift[0][i]);
-        f[(long long)i * g.Npad + n] = store_t<ST>(0);
-      }
-      mask[n] = 1;
-      sign = 1.0;
-    } else {
-      const double* v = ps.vel + 3 * p;
-      const double* w = ps.omg + 3 * p;
-      const double ub[3] = {v[0] + (w[1] * d[2] - w[2] * d[1]), v[1] + (w[2] * d[0] - w[0] * d[2]),
-                            v[2] + (w[0] * d[1] - w[1] * d[0])};
-      const real ux = static_cast<real>(ub[0]), uy = static_cast<real>(ub[1]), uz = static_cast<real>(ub[2]);
-      const real rho0 = static_cast<real>(ps.rho0);
-      const real t15 = real(1.5) * ((ux * ux + uy * uy) + uz * uz);
+    for (int kc = 0; kc < NC; ++kc) {
+      const long long kp = (long long)(kc * Q) * g.Npad;
+      real vals[Q];
+      double sign;
+      if (covered) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const real cu = cdot<real>(i, ux, uy, uz);
-        const real feq = (weight<real>(i) * rho0) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
-        const store_t<ST> s = encode<ST>(feq, c.shift[0][i]);
-        f[(long long)i * g.Npad + n] = s;
-        vals[i] = decode<ST>(s, c.shift[0][i]);  // the stored value, so that the exchange is exact
+        for (int i = 0; i < Q; ++i) {
+          vals[i] = decode<ST>(f[kp + (long long)i * g.Npad + n], c.shift[kc][i]);
+          f[kp + (long long)i * g.Npad + n] = store_t<ST>(0);
+        }
+        sign = 1.0;
+      } else {
+        const double* v = ps.vel + 3 * p;
+        const double* w = ps.omg + 3 * p;
+        const double ub[3] = {v[0] + (w[1] * d[2] - w[2] * d[1]), v[1] + (w[2] * d[0] - w[0] * d[2]),
+                              v[2] + (w[0] * d[1] - w[1] * d[0])};
+        const real ux = static_cast<real>(ub[0]), uy = static_cast<real>(ub[1]), uz = static_cast<real>(ub[2]);
+        const real rho0 = static_cast<real>(ps.rho0[kc]);
+        const real t15 = real(1.5) * ((ux * ux + uy * uy) + uz * uz);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const real cu = cdot<real>(i, ux, uy, uz);
+          const real feq = (weight<real>(i) * rho0) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
+          const store_t<ST> sv = encode<ST>(feq, c.shift[kc][i]);
+          f[kp + (long long)i * g.Npad + n] = sv;
+          vals[i] = decode<ST>(sv, c.shift[kc][i]);  // the stored value, so that the exchange is exact
+        }
+        sign = -1.0;
       }
-      mask[n] = 0;
-      sign = -1.0;
+      const double m[3] = {sign * static_cast<double>(lattice_sum<0, 0, real>(vals)),
+                           sign * static_cast<double>(lattice_sum<1, 0, real>(vals)),
+                           sign * static_cast<double>(lattice_sum<2, 0, real>(vals))};
+      acc[0] = acc[0] + m[0];
+      acc[1] = acc[1] + m[1];
+      acc[2] = acc[2] + m[2];
+      acc[3] = acc[3] + (d[1] * m[2] - d[2] * m[1]);
+      acc[4] = acc[4] + (d[2] * m[0] - d[0] * m[2]);
+      acc[5] = acc[5] + (d[0] * m[1] - d[1] * m[0]);
     }
-    const double m[3] = {sign * static_cast<double>(lattice_sum<0, 0, real>(vals)),
-                         sign * static_cast<double>(lattice_sum<1, 0, real>(vals)),
-                         sign * static_cast<double>(lattice_sum<2, 0, real>(vals))};
-    acc[0] = acc[0] + m[0];
-    acc[1] = acc[1] + m[1];
-    acc[2] = acc[2] + m[2];
-    acc[3] = acc[3] + (d[1] * m[2] - d[2] * m[1]);
-    acc[4] = acc[4] + (d[2] * m[0] - d[0] * m[2]);
-    acc[5] = acc[5] + (d[0] * m[1] - d[1] * m[0]);
   }
   part_reduce(acc, red);
   if (threadIdx.x == 0) {
@@ -421,8 +443,9 @@ __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict
   }
 }
 
-// Initial owner-based state: zero the populations of solid nodes, mask = owner != fluid.
-template <int ST>
+// Initial owner-based state: zero the populations of solid nodes (NC
+// components), mask = owner != fluid.
+template <int ST, int NC = 1>
 __global__ void __launch_bounds__(kBlock) kp_apply_owner(store_t<ST>* __restrict__ f, const int* __restrict__ owner,
                                                          uint8_t* __restrict__ mask, Geometry g) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
@@ -431,20 +454,23 @@ __global__ void __launch_bounds__(kBlock) kp_apply_owner(store_t<ST>* __restrict
   mask[n] = solid ? 1 : 0;
   if (solid)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[(long long)i * g.Npad + n] = store_t<ST>(0);
+    for (int i = 0; i < NC * Q; ++i) f[(long long)i * g.Npad + n] = store_t<ST>(0);
 }
 
-// Particles removed: their nodes turn to fluid at rest, f_i = w_i rho0.
-template <int ST>
+// Particles removed: their nodes turn to fluid at rest, f^k_i = w_i rho0_k.
+template <int ST, int NC = 1>
 __global__ void __launch_bounds__(kBlock) kp_release(store_t<ST>* __restrict__ f, uint8_t* __restrict__ mask,
-                                                     double rho0, Geometry g, StepCoeffs c) {
+                                                     double rho0a, double rho0b, Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N || !mask[n]) return;
   mask[n] = 0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    f[(long long)i * g.Npad + n] = encode<ST>(weight<real>(i) * static_cast<real>(rho0), c.shift[0][i]);
+  for (int kc = 0; kc < NC; ++kc)
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      f[(long long)(kc * Q + i) * g.Npad + n] =
+          encode<ST>(weight<real>(i) * static_cast<real>(kc == 0 ? rho0a : rho0b), c.shift[kc][i]);
 }
 
 }  // namespace lbd

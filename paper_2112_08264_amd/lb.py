@@ -95,6 +95,8 @@ _SIGNATURES = [
     ("lb1_totals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     ("lb1_set_particles", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     ("lb1_get_particles", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("lb_set_particles", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    ("lb_get_particles", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("lb_snapshot_totals", ctypes.c_int, [ctypes.POINTER(lb_params), _P, _P, _P, ctypes.c_int32]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_abi_version", ctypes.c_int32, []),
@@ -445,26 +447,46 @@ def _host3(a, count: int, what: str):
     return arr
 
 
-def lb1_set_particles(ctx, pos, radius: float, mass: float, vel=None, omega=None) -> None:
-    """Place rigid spheres (host arrays [P][3]); pos=None or empty removes them."""
+def _set_particles(name: str, ctx, pos, radius: float, mass: float, vel=None, omega=None) -> None:
     import numpy as np
 
+    fn = getattr(library(), name)
     if pos is None or np.size(pos) == 0:
-        _check(library().lb1_set_particles(ctx, 0, float(radius), float(mass), None, None, None), "lb1_set_particles")
+        _check(fn(ctx, 0, float(radius), float(mass), None, None, None), name)
         return
     count = np.size(pos) // 3
     arrs = [_host3(a, count, w) for a, w in ((pos, "pos"), (vel, "vel"), (omega, "omega"))]
     ptrs = [None if a is None else ctypes.c_void_p(a.ctypes.data) for a in arrs]
-    _check(library().lb1_set_particles(ctx, count, float(radius), float(mass), *ptrs), "lb1_set_particles")
+    _check(fn(ctx, count, float(radius), float(mass), *ptrs), name)
+
+
+def _get_particles(name: str, ctx, count: int):
+    import numpy as np
+
+    outs = [np.empty((count, 3)) for _ in range(5)]
+    _check(getattr(library(), name)(ctx, *[ctypes.c_void_p(o.ctypes.data) for o in outs]), name)
+    return tuple(outs)
+
+
+def lb1_set_particles(ctx, pos, radius: float, mass: float, vel=None, omega=None) -> None:
+    """Place rigid spheres (host arrays [P][3]); pos=None or empty removes them."""
+    _set_particles("lb1_set_particles", ctx, pos, radius, mass, vel, omega)
 
 
 def lb1_get_particles(ctx, count: int):
     """(pos, vel, omega, force, torque), each a host float64 array [count][3]."""
-    import numpy as np
+    return _get_particles("lb1_get_particles", ctx, count)
 
-    outs = [np.empty((count, 3)) for _ in range(5)]
-    _check(library().lb1_get_particles(ctx, *[ctypes.c_void_p(o.ctypes.data) for o in outs]), "lb1_get_particles")
-    return tuple(outs)
+
+def lb_set_particles(ctx, pos, radius: float, mass: float, vel=None, omega=None) -> None:
+    """Place rigid spheres in a colour-gradient context (host arrays [P][3]);
+    pos=None or empty removes them."""
+    _set_particles("lb_set_particles", ctx, pos, radius, mass, vel, omega)
+
+
+def lb_get_particles(ctx, count: int):
+    """(pos, vel, omega, force, torque) of a two-component context's particles."""
+    return _get_particles("lb_get_particles", ctx, count)
 
 
 class SingleFluid:
@@ -551,6 +573,7 @@ class Lattice:
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
         self.params = p
+        self.nparticles = 0
         self.ctx = lb_create(p)
         try:
             lb_set_kernel(self.ctx, kernel)
@@ -578,6 +601,7 @@ class Lattice:
 
     def set_fields(self, rho_a, rho_b, u=None, solid=None):
         lb_set_fields(self.ctx, self.n, rho_a, rho_b, u, solid)
+        self.nparticles = 0  # new fields drop the particles
 
     def step(self, nsteps: int = 1):
         lb_step(self.ctx, nsteps)
@@ -593,3 +617,15 @@ class Lattice:
 
     def totals(self):
         return lb_totals(self.ctx)
+
+    def set_particles(self, pos, radius: float, mass: float, vel=None, omega=None):
+        """Rigid spheres in the colour-gradient fluid (host arrays [P][3]);
+        pos=None removes them."""
+        import numpy as np
+
+        lb_set_particles(self.ctx, pos, radius, mass, vel, omega)
+        self.nparticles = 0 if pos is None else int(np.size(pos) // 3)
+
+    def particles(self):
+        """(pos, vel, omega, force, torque) of the particles, host [P][3] each."""
+        return lb_get_particles(self.ctx, self.nparticles)

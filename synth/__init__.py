@@ -86,6 +86,17 @@ WORKLOADS = {
                                spheres=2407, radius=5.5, sphere_seed=14),
     "case3c_256_f64": Workload("case3c_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.02, 500, 11,
                                spheres=2407, radius=5.5, sphere_seed=14),
+    # the paper's case 3: moving rigid spheres of radius 5.5 in the two immiscible fluids of case 2 (every
+    # node pure red or pure blue at random, at rest), 0.1%, 1% and 10% of a 256^3 box (the sphere positions
+    # of the single-fluid workloads above); uncovered nodes start at rho0 = (1/2, 1/2)
+    "case3cg_a_256_f32": Workload("case3cg_a_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (0.5, 0.5), 0.0,
+                                  500, 10, spheres=24, radius=5.5, sphere_seed=12, sigma=0.01, beta=0.7),
+    "case3cg_b_256_f32": Workload("case3cg_b_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (0.5, 0.5), 0.0,
+                                  500, 10, spheres=241, radius=5.5, sphere_seed=13, sigma=0.01, beta=0.7),
+    "case3cg_c_256_f32": Workload("case3cg_c_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (0.5, 0.5), 0.0,
+                                  500, 10, spheres=2407, radius=5.5, sphere_seed=14, sigma=0.01, beta=0.7),
+    "case3cg_c_256_f64": Workload("case3cg_c_256_f64", (256, 256, 256), "f64", (1.0, 1.0), 0.0, (0.5, 0.5), 0.0,
+                                  500, 10, spheres=2407, radius=5.5, sphere_seed=14, sigma=0.01, beta=0.7),
     "case2_32_f64": Workload("case2_32_f64", (32, 32, 32), "f64", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 200, 9,
                              sigma=0.01, beta=0.7),
     "case2_256_f32": Workload("case2_256_f32", (256, 256, 256), "f32", (1.0, 1.0), 0.0, (1.0, 1.0), 0.0, 1000, 10,

@@ -1,0 +1,325 @@
+"""Parity of moving particles in the colour-gradient fluid (lb_set_particles /
+lb_step through the C ABI, the paper's case 3) with the FP64 oracle
+``oracle/lb_cg_particles.py``.
+
+The oracle sums each particle's force, torque and covering momentum exactly
+and rounds once (math.fsum); the GPU sums the same float64 terms in its own
+order.  After one step from a shared state the forces and torques may differ
+by at most the summation bound of the oracle's own terms (``PT.sum_bound``),
+and every population the sums do not reach is bitwise equal.  Over 15 steps
+the states are held to the 1e-12 relative-per-population bar and the
+particle state to 1e-12 absolute.  float32 is held to bounds from its
+precision.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2112_08264_amd as P
+from oracle import lb_cg_particles as CP
+from oracle import lb_oracle as O
+from oracle import lb_particles as PT
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mixture(shape, seed, amp=0.3, vel=0.01):
+    """A partly mixed two-fluid state (every node has both components) with a
+    small random flow."""
+    rng = np.random.default_rng(seed)
+    c = 0.5 + rng.uniform(-amp, amp, shape)
+    rho = 1.0 + rng.uniform(-0.02, 0.02, shape)
+    u = [rng.uniform(-vel, vel, shape) for _ in range(3)]
+    return rho * c, rho * (1.0 - c), u
+
+
+def _lattice(shape, p: CP.Params, storage="f64"):
+    return P.Lattice(shape, tau=p.tau, storage=storage, model="colour_gradient", sigma=p.sigma, beta=p.beta,
+                     rho0=p.rho0)
+
+
+def run_gpu(shape, p, r1, r2, u, part, steps, storage="f64"):
+    torch = _torch()
+    n = int(np.prod(shape))
+    with _lattice(shape, p, storage) as lat:
+        uu = None if u is None else np.ascontiguousarray(np.stack(u).reshape(-1))
+        lat.set_fields(np.ascontiguousarray(r1.reshape(-1)), np.ascontiguousarray(r2.reshape(-1)), uu)
+        lat.set_particles(part.pos, part.radius, part.mass, part.vel, part.omg)
+        lat.step(steps)
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        torch.cuda.synchronize()
+        return f.cpu().numpy().reshape((2, 19) + tuple(shape)), lat.particles()
+
+
+PAR = CP.Params((1.0, 0.9), 0.01, 0.7, (0.5, 0.5))
+
+CASES = {
+    # two particles crossing nodes
+    "two": ((20, 18, 22), PT.Particles(3.2, 400.0, [[6.3, 5.2, 7.1], [15.4, 12.6, 13.2]],
+                                       [[0.08, -0.05, 0.06], [-0.07, 0.06, -0.05]],
+                                       [[0.0, 0.0, 0.02], [0.02, -0.01, 0.0]])),
+    # three particles, two of them across the periodic boundaries
+    "wrap": ((19, 21, 24), PT.Particles(2.7, 250.0, [[0.4, 10.2, 18.7], [22.9, 20.6, 3.3], [12.0, 5.5, 9.9]],
+                                        [[-0.12, 0.03, 0.09], [0.1, 0.11, -0.04], [0.0, 0.1, 0.0]],
+                                        [[0.01, 0.02, -0.01], [0.0, 0.0, 0.0], [-0.02, 0.0, 0.03]])),
+    # two spheres under one node apart: fluid nodes between them have links into both
+    "close": ((16, 18, 28), PT.Particles(3.3, 400.0, [[8.2, 9.1, 8.4], [15.6, 9.4, 8.0]],
+                                         [[0.03, 0.0, 0.01], [-0.03, 0.01, 0.0]],
+                                         [[0.0, 0.01, 0.0], [0.01, 0.0, -0.01]])),
+    # two overlapping spheres: nodes inside both belong to the lower index
+    "overlap": ((18, 18, 22), PT.Particles(3.1, 400.0, [[9.3, 8.8, 9.1], [13.4, 9.6, 9.0]],
+                                           [[0.02, 0.0, 0.0], [0.02, 0.01, 0.0]], None)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_f64_first_step_within_the_summation_bound(name):
+    """One step from the shared initial state.  The fluid step before the sums
+    is bitwise equal, so the GPU's force and torque lie within the summation
+    bound of the oracle's own link terms, velocities and positions within that
+    bound carried through the leap-frog and the covering sums, and every
+    population not at a node uncovered in the step is bitwise equal."""
+    shape, part = CASES[name]
+    _say(f"case cg particles f64 first step {name} shape={shape}")
+    r1, r2, u = _mixture(shape, 61)
+    f, owner = CP.init(r1, r2, part, u)
+    fnew, rho_t = CP.fluid_step(f, PAR, part, owner)
+    nP = part.pos.shape[0]
+    bF = np.array([PT.sum_bound(CP.link_terms(fnew, rho_t, part, owner, p)) for p in range(nP)])
+    F, T = CP.link_forces(fnew, rho_t, part, owner)
+    q = PT.move(part, F, T, shape)
+    owner1 = PT.owner_map(shape, q)
+    bC = np.array([PT.sum_bound(CP.remap_terms(fnew.copy(), q, owner, owner1, PAR.rho0, p)) for p in range(nP)])
+    ref = CP.remap(fnew, q, owner, owner1, PAR.rho0)
+    got, (pos, vel, omg, force, torque) = run_gpu(shape, PAR, r1, r2, u, part, 1)
+    assert np.all(np.abs(force - F) <= bF[:, :3])
+    assert np.all(np.abs(torque - T) <= bF[:, 3:])
+    m, inertia = part.mass, part.inertia
+    tol_v = (bF[:, :3] + bC[:, :3]) / m + 8 * U * (np.abs(q.vel) + np.abs(F) / m + np.abs(part.vel))
+    tol_w = (bF[:, 3:] + bC[:, 3:]) / inertia + 8 * U * (np.abs(q.omg) + np.abs(T) / inertia + np.abs(part.omg))
+    assert np.all(np.abs(vel - q.vel) <= tol_v)
+    assert np.all(np.abs(omg - q.omg) <= tol_w)
+    assert np.all(np.abs(pos - q.pos) <= bF[:, :3] / m + 8 * U * (np.abs(q.pos) + 1.0))
+    uncovered = (owner != PT.FLUID) & (owner1 == PT.FLUID)
+    keep = ~uncovered
+    assert np.array_equal(got[:, :, keep], ref[:, :, keep])
+    if np.any(uncovered):
+        assert O.population_error(got[:, :, uncovered], ref[:, :, uncovered]) <= 1e-13
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_f64_matches_oracle_over_15_steps(name):
+    shape, part = CASES[name]
+    _say(f"case cg particles f64 15 steps {name} shape={shape}")
+    r1, r2, u = _mixture(shape, 62)
+    f, owner = CP.init(r1, r2, part, u)
+    ref, q, owner_end = CP.step(f, PAR, part.copy(), owner, n=15)
+    assert np.all(np.isfinite(ref))
+    got, (pos, vel, omg, force, torque) = run_gpu(shape, PAR, r1, r2, u, part, 15)
+    assert np.sum(owner_end != owner) > 0
+    perr = O.population_error(got, ref)
+    serr = max(float(np.max(np.abs(a - b))) for a, b in ((pos, q.pos), (vel, q.vel), (omg, q.omg),
+                                                          (force, q.force), (torque, q.torque)))
+    _say(f"  population error {perr:.1e}, particle state {serr:.1e}")
+    assert perr <= 1e-12
+    assert serr <= 1e-12
+
+
+def test_f64_demixing_start_with_particles_over_15_steps():
+    """The case-3 start (every node pure red or pure blue) with moving spheres:
+    fluid nodes next to a pure node of the other colour have a phase-field
+    gradient from the first step, and the wetting rule meets real interfaces."""
+    shape, part = CASES["two"]
+    _say(f"case cg particles f64 case-3 start shape={shape}")
+    r1, r2 = synth.colour_fields(shape, 63)
+    f, owner = CP.init(r1, r2, part)
+    ref, q, _ = CP.step(f, PAR, part.copy(), owner, n=15)
+    got, (pos, vel, *_r) = run_gpu(shape, PAR, r1, r2, None, part, 15)
+    perr = O.population_error(got, ref)
+    _say(f"  population error {perr:.1e}, |dpos| {np.max(np.abs(pos - q.pos)):.1e}")
+    assert perr <= 1e-12
+    assert np.max(np.abs(pos - q.pos)) <= 1e-12
+    assert np.max(np.abs(vel - q.vel)) <= 1e-12
+
+
+def test_f64_resting_particle_is_the_fixed_solid_step():
+    """A particle of infinite mass at rest: the moving-wall terms vanish and the
+    step is the oracle's colour-gradient step with fixed solid nodes, bitwise."""
+    shape = (14, 15, 16)
+    _say(f"case cg particles f64 resting shape={shape}")
+    r1, r2, u = _mixture(shape, 64)
+    part = PT.Particles(3.5, math.inf, [[7.0, 6.5, 8.2]], None, None)
+    f, owner = CP.init(r1, r2, part, u)
+    ref = CP.step_solid(f, PAR, owner != PT.FLUID, n=6)
+    got, (pos, *_rest) = run_gpu(shape, PAR, r1, r2, u, part, 6)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(pos, part.pos)
+
+
+def test_f64_total_momentum_conserved_with_many_particles():
+    shape = (48, 48, 48)
+    _say(f"case cg particles f64 momentum shape={shape}")
+    rng = np.random.default_rng(65)
+    centres = synth.sphere_centres(shape, 20, 3.5, 66, min_sep=9.0)
+    vel = rng.uniform(-0.05, 0.05, (20, 3))
+    omg = rng.uniform(-0.01, 0.01, (20, 3))
+    r1, r2 = synth.colour_fields(shape, 67)
+    mass = synth.particle_mass(3.5)
+    with _lattice(shape, PAR) as lat:
+        lat.set_fields(r1.ravel().copy(), r2.ravel().copy())
+        lat.set_particles(centres, 3.5, mass, vel, omg)
+
+        def total():
+            (MA, MB, px, py, pz), nonfinite = lat.totals()
+            assert not nonfinite
+            _, v, *_ = lat.particles()
+            return MA + MB, np.array([px, py, pz]) + mass * v.sum(axis=0)
+
+        M0, P0 = total()
+        lat.step(100)
+        M1, P1 = total()
+    _say(f"  |dP| {np.max(np.abs(P1 - P0)):.2e}, dM/M {abs(M1 - M0) / M0:.2e}")
+    assert np.max(np.abs(P1 - P0)) <= 1e-12 * M0
+    assert abs(M1 - M0) <= 1e-3 * M0  # uncovered nodes start at rho0: mass is not conserved exactly
+
+
+def test_f32_against_the_oracle():
+    """float32 fluid with float64 particle arithmetic, 15 steps: positions
+    within 1e-6 and populations within 1e-5 of the float64 oracle (float32
+    rounds each population to 2^-24 relative; forces sum a few hundred links
+    of such values)."""
+    shape, part = CASES["two"]
+    _say(f"case cg particles f32 shape={shape}")
+    r1, r2, u = _mixture(shape, 68)
+    f, owner = CP.init(r1, r2, part, u)
+    ref, q, _ = CP.step(f, PAR, part.copy(), owner, n=15)
+    got, (pos, vel, *_rest) = run_gpu(shape, PAR, r1, r2, u, part, 15, storage="f32")
+    perr = float(np.max(np.abs(pos - q.pos)))
+    ferr = float(np.max(np.abs(got - ref)))
+    _say(f"  max |dpos| {perr:.2e}, max |df| {ferr:.2e}")
+    assert perr <= 1e-6
+    assert ferr <= 1e-5
+
+
+def test_moments_and_totals_with_particles():
+    """lb_moments reports zero at particle nodes and the oracle's moments at
+    fluid nodes; lb_totals sums the fluid."""
+    torch = _torch()
+    shape, part = CASES["wrap"]
+    n = int(np.prod(shape))
+    r1, r2, u = _mixture(shape, 69)
+    f, owner = CP.init(r1, r2, part, u)
+    ref, q, owner_end = CP.step(f, PAR, part.copy(), owner, n=3)
+    solid = owner_end != PT.FLUID
+    with _lattice(shape, PAR) as lat:
+        lat.set_fields(r1.ravel().copy(), r2.ravel().copy(), np.stack(u).reshape(-1).copy())
+        lat.set_particles(part.pos, part.radius, part.mass, part.vel, part.omg)
+        lat.step(3)
+        ra, rb, uu = np.empty(n), np.empty(n), np.empty(3 * n)
+        lat.moments(ra, rb, uu)
+        tot, nonfinite = lat.totals()
+    assert not nonfinite
+    ra, rb = ra.reshape(shape), rb.reshape(shape)
+    assert np.all(ra[solid] == 0.0) and np.all(rb[solid] == 0.0)
+    assert np.all(uu.reshape((3,) + shape)[:, solid] == 0.0)
+    np.testing.assert_allclose(ra[~solid], O.density(ref[0])[~solid], rtol=1e-12)
+    np.testing.assert_allclose(rb[~solid], O.density(ref[1])[~solid], rtol=1e-12)
+    want, _ = O.totals(ref)
+    np.testing.assert_allclose(tot[:2], want[:2], rtol=1e-12)
+
+
+def test_cg_particle_error_paths():
+    shape = (16, 16, 16)
+    n = 16 ** 3
+    good = np.array([[8.0, 8.0, 8.0]])
+    half = np.full(n, 0.5)
+    with P.Lattice(shape) as lat:  # Shan-Chen model: no particles
+        lat.set_fields(half, half)
+        with pytest.raises(P.LBError) as e:
+            lat.set_particles(good, 2.0, 10.0)
+        assert e.value.status == P.LB_EINVAL
+    with _lattice(shape, PAR) as lat:
+        with pytest.raises(P.LBError) as e:
+            lat.set_particles(good, 2.0, 10.0)
+        assert e.value.status == P.LB_ESTATE
+        lat.set_fields(half, half)
+        for args in ((good, 6.5, 10.0), (good, -1.0, 10.0), (good, 2.0, 0.0), (good, 2.0, float("nan")),
+                     (np.array([[16.0, 8.0, 8.0]]), 2.0, 10.0)):
+            with pytest.raises(P.LBError) as e:
+                lat.set_particles(*args)
+            assert e.value.status == P.LB_EINVAL
+        with pytest.raises(P.LBError) as e:
+            lat.particles()
+        assert e.value.status == P.LB_ESTATE
+        lat.set_particles(good, 2.0, math.inf)
+        with pytest.raises(P.LBError) as e:  # back to Shan-Chen while particles are placed
+            P.lb_set_model(lat.ctx, "shan_chen")
+        assert e.value.status == P.LB_EINVAL
+        buf = np.empty(P.lb_state_bytes(lat.ctx), dtype=np.uint8)
+        P.lb_save_state(lat.ctx, buf)
+        with pytest.raises(P.LBError) as e:
+            P.lb_restore_state(lat.ctx, buf)
+        assert e.value.status == P.LB_EINVAL
+        lat.step(2)
+        pos, *_ = lat.particles()
+        assert np.array_equal(pos, good)
+        lat.set_particles(None, 2.0, 1.0)  # removes them: their nodes turn to fluid at rest
+        lat.step(1)
+        tot, nonfinite = lat.totals()
+        assert not nonfinite
+
+
+@pytest.mark.parametrize("name", ["case3cg_c_256_f32", "case3cg_c_256_f64"])
+def test_full_size_case3_conserves_momentum(name):
+    """The 10% workload of the paper's case 3 (2407 moving spheres of radius
+    5.5 in the 256^3 two-fluid box), in the launch configuration the
+    benchmark times, set moving: 20 steps keep the total momentum (fluid plus
+    particles) to rounding, every particle inside the box and the state
+    finite."""
+    w = synth.WORKLOADS[name]
+    _say(f"case {w.name} momentum")
+    r1, r2 = synth.colour_fields(w.shape, w.seed)
+    centres = synth.sphere_centres(w.shape, w.spheres, w.radius, w.sphere_seed)
+    rng = np.random.default_rng(70)
+    vel = rng.uniform(-0.02, 0.02, (w.spheres, 3))
+    mass = synth.particle_mass(w.radius)
+    p = CP.Params(w.tau, w.sigma, w.beta, w.rho0)
+    with _lattice(w.shape, p, w.storage) as lat:
+        lat.set_fields(r1.ravel(), r2.ravel())
+        lat.set_particles(centres, w.radius, mass, vel)
+
+        def total():
+            (MA, MB, px, py, pz), nonfinite = lat.totals()
+            assert not nonfinite
+            pos, v, *_ = lat.particles()
+            return MA + MB, np.array([px, py, pz]) + mass * v.sum(axis=0), pos
+
+        M0, P0, _ = total()
+        lat.step(20)
+        M1, P1, pos = total()
+    drift = float(np.max(np.abs(P1 - P0)))
+    # rounding random walk: each step rounds every population once (float32: 2^-24, float64: 2^-53
+    # relative), about 19 * 2 populations of size ~w_i per node over N nodes
+    eps = 2.0 ** -24 if w.storage == "f32" else 2.0 ** -53
+    bound = 20 * eps * math.sqrt(2 * 19 * w.nodes) * 10.0
+    _say(f"  |dP| {drift:.2e} (bound {bound:.2e}), dM/M {abs(M1 - M0) / M0:.2e}")
+    assert drift <= bound
+    assert np.all((pos >= 0.0) & (pos < 256.0))
