@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "GLUPS & % HBM roofline, 2-comp D3Q19 256^3; adjoint/forward time ratio"
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2}
 KERNEL_SOURCES = ["paper_2112_08264_amd/csrc/lb_device.h", "paper_2112_08264_amd/csrc/lb_kernels.h",
-                  "paper_2112_08264_amd/csrc/lb_fused.h",
+                  "paper_2112_08264_amd/csrc/lb_fused.h", "paper_2112_08264_amd/csrc/lb_adjoint.h",
+                  "paper_2112_08264_amd/csrc/lb_particles.h", "paper_2112_08264_amd/csrc/lb_single.h",
                   "paper_2112_08264_amd/csrc/lb_api.hip"]
 
 
@@ -1063,6 +1064,8 @@ def main(argv=None) -> int:
             if st in forms:
                 forms[st]["error_vs_f64"] = accuracy[st]["trajectory"]
                 forms[st]["error_vs_f64_restart"] = accuracy[st]["restart"]
+                forms[st]["first_step_over_1e-3"] = accuracy[st]["first_step_over_1e-3"]
+                forms[st]["restart_first_step_over_1e-3"] = accuracy[st]["restart_first_step_over_1e-3"]
 
     adjoint = None
     if not args.no_adjoint:

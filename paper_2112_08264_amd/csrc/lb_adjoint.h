@@ -72,9 +72,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_moments(const store_t<ST>* __res
 }
 
 // Local part.  lam_in = lam(t+1), lam_out = lam(t) without the stencil term;
-// W = [6][N] (W_A then W_B); partial[block] = the block's dJ/dG sum (float64).
+// W = [6][N] (W_A then W_B); partial[block] += the block's dJ/dG sum of this
+// step (float64; each block owns its slot, so the running sums of a whole
+// backward pass are folded once, at the end).
+// float64: capped at 256 registers for two waves per SIMD (left alone the
+// compiler takes 264 and one wave; 8 spills instead: 470 -> ~410 us per
+// adjoint step at 128^3).
 template <int ST>
-__global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restrict__ lam_in, const real_t<ST>* __restrict__ r_in,
+__global__ void __launch_bounds__(kBlock, ST == ST_F64 ? 2 : 1) k_adj_local(const real_t<ST>* __restrict__ lam_in, const real_t<ST>* __restrict__ r_in,
                                                       real_t<ST>* __restrict__ lam_out, const real_t<ST>* __restrict__ mom,
                                                       const uint8_t* __restrict__ mask, real_t<ST>* __restrict__ Wout,
                                                       double* __restrict__ partial, Geometry g, StepCoeffs c) {
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_local(const real_t<ST>* __restri
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) t += red[w];
-    partial[blockIdx.x] = t;
+    partial[blockIdx.x] = partial[blockIdx.x] + t;
   }
 }
 
@@ -232,7 +237,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_r(const real_t<ST>* __restrict__
   }
 }
 
-// Fold one step's block partials into the running dJ/dG (single block, fixed order).
+// dJ/dG of the adjoint steps so far: the blocks' running sums folded in a
+// fixed order (single block); acc[0] is overwritten, so folding twice gives
+// the same value.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ partial, int blocks, double* __restrict__ acc) {
   double s = 0.0;
   for (int b = threadIdx.x; b < blocks; b += kBlock) s += partial[b];
@@ -243,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int q = 0; q < kBlock / 64; ++q) t += red[q];
-    acc[0] += t;
+    acc[0] = t;
   }
 }
 

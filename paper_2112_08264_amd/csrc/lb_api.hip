@@ -56,6 +56,12 @@ constexpr int kFloatTallMinChunk = 64;
 // (float32) and 1.5% (float16) faster than three at 256^3 (fewer registers,
 // 133 against 152).
 constexpr int kFloatDepth = 2;
+// float32 without solids on the tile-major layout: loads issued two
+// iterations before their plane's psi is published (LEAD = 2, 168
+// registers, so 64 x 4 tiles at two waves per SIMD): 1.056 -> 0.985 ms at
+// 256^3 against 64 x 8 tiles with one iteration of lead.  float16-shifted
+// went the other way (0.729 -> 0.794 ms) and keeps the 64 x 8 tiles.
+constexpr int kFloat32Lead = 2;
 // Staged float64 step on 64 x 4 tiles (two waves per row) where nx allows:
 // 9% faster than 32 x 8 at 256^3 -- half as many tile edges in x, where a
 // push store writes a 128-byte line only in part.  The unstaged kernel was
@@ -253,12 +259,12 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
                      bool tiled = false) {
   const uint8_t* m = SOLID ? ctx->mask : nullptr;
   if constexpr (ST == ST_F64) {
-    if constexpr (!SOLID && !RECORD) {
+    if constexpr (!SOLID) {
       if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
         const FusedTiling t = ctx->tiling_wide;
-        k_fused_pair<ST, false, kWideTY, false, true, kWideTX, kModelSC, true>
+        k_fused_pair<ST, false, kWideTY, RECORD, true, kWideTX, kModelSC, true>
             <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
-                                                                               nullptr);
+                                                                               rec);
         return;
       }
     }
@@ -291,6 +297,13 @@ void launch_fused_as(lb_ctx* ctx, const typename StorageTraits<ST>::store_t* fin
     }
     if constexpr (!SOLID) {
       if (tiled) {  // the caller has checked tiled_ok and put the grids in the tile-major layout
+        if constexpr (ST == ST_F32) {
+          const FusedTiling t = ctx->tiling;
+          k_fused<ST, false, kFloatTY, kFloatDepth, RECORD, kFloatTX, true, kFloat32Lead>
+              <<<dim3(t.total), dim3(128 * kFloatTY * kFloatTX / 64), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g,
+                                                                                         ctx->c, t, rec);
+          return;
+        }
         if (ctx->tall) {
           const FusedTiling t = ctx->tiling_tall;
           k_fused<ST, false, kFloatTallTY, kFloatDepth, RECORD, kFloatTX, true>
@@ -658,6 +671,7 @@ lb_status adjoint_begin_impl(lb_ctx* ctx, const double* ga, const double* gb) {
       ga, gb, mask_or_null(ctx), static_cast<real*>(ctx->lam[0]), static_cast<real*>(ctx->rbuf), ctx->g);
   LB_HIP(hipGetLastError());
   LB_HIP(hipMemsetAsync(ctx->adj_dG, 0, sizeof(double) * 2, ctx->stream));
+  LB_HIP(hipMemsetAsync(ctx->adj_partial, 0, sizeof(double) * blocks_for(ctx->g.N), ctx->stream));
   return LB_OK;
 }
 
@@ -677,8 +691,6 @@ lb_status adjoint_record_step_impl(lb_ctx* ctx, const typename StorageTraits<ST>
   if (st != LB_OK) return st;
   st = launch(ctx, SLOT_ADJ_R, [&] { k_adj_r<ST><<<nb, kBlock, 0, ctx->stream>>>(mom, W, m, r, ctx->g, ctx->c); });
   if (st != LB_OK) return st;
-  k_adj_fold<<<1, kBlock, 0, ctx->stream>>>(ctx->adj_partial, nb, ctx->adj_dG);
-  LB_HIP(hipGetLastError());
   ctx->lam_cur ^= 1;
   return LB_OK;
 }
@@ -707,9 +719,9 @@ lb_status step_record_impl(lb_ctx* ctx, void* record) {
   real* rec = static_cast<real*>(record);
   lb_status st;
   if (use_fused(ctx)) {
-    // the float kernel records on the tile-major layout too (the record is
-    // indexed by node); the float64 record step runs on the structure of arrays
-    const bool tiled = ST != ST_F64 && tiled_ok(ctx);
+    // the record step runs on the tile-major layout where the plain step
+    // does (the record itself is indexed by node, whatever the layout)
+    const bool tiled = tiled_ok(ctx);
     st = set_layout(ctx, tiled);
     if (st != LB_OK) return st;
     fin = static_cast<const store*>(ctx->grid[ctx->cur]);
@@ -1615,6 +1627,8 @@ lb_status lb_adjoint_result(lb_ctx* ctx, double* dJ_drho_a0, double* dJ_drho_b0,
   }
   if (dJ_dG != nullptr) {
     double v = 0.0;
+    k_adj_fold<<<1, kBlock, 0, ctx->stream>>>(ctx->adj_partial, blocks_for(ctx->g.N), ctx->adj_dG);
+    LB_HIP(hipGetLastError());
     LB_HIP(hipMemcpyAsync(&v, ctx->adj_dG, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     LB_HIP(hipStreamSynchronize(ctx->stream));
     *dJ_dG = v;

@@ -93,6 +93,65 @@ __device__ __forceinline__ typename StorageTraits<ST>::store_t encode(typename S
   }
 }
 
+// 1.0f in a register whose value the compiler does not know.  With it,
+// fma(float(h), one, shift) is selected as one v_fma_mix_f32 (the float16
+// operand converted inside the FMA, one rounding of h + shift: the same bits
+// as the conversion followed by the float32 addition of `decode`), where
+// the visible 1.0 would be folded into a plain addition.
+__device__ __forceinline__ float opaque_one() {
+  float one;
+  asm volatile("v_mov_b32 %0, 1.0" : "=v"(one));
+  return one;
+}
+
+// `decode` for a uniform shift, with `one` from opaque_one().
+template <int ST>
+__device__ __forceinline__ typename StorageTraits<ST>::real decode_mix(typename StorageTraits<ST>::store_t v,
+                                                                      float shift, float one) {
+  if constexpr (ST == ST_F16S) {
+    return __builtin_fmaf(__half2float(v), one, shift);
+  } else {
+    (void)shift;
+    (void)one;
+    return v;
+  }
+}
+
+// Raw buffer access (gfx9 resource descriptor, stride 0): the wave-uniform
+// base goes into the descriptor and the soffset register, the per-lane
+// part into a 32-bit voffset, so no 64-bit address is formed per lane.
+// Accesses at or beyond `bytes` from the base read 0 and write nothing.
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
+}
+
+template <int ST>
+__device__ __forceinline__ typename StorageTraits<ST>::store_t buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                                          uint32_t soff) {
+  if constexpr (ST == ST_F16S) {
+    return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  } else if constexpr (ST == ST_F32) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void buffer_store(typename StorageTraits<ST>::store_t v, __amdgpu_buffer_rsrc_t r,
+                                             uint32_t voff, uint32_t soff) {
+  if constexpr (ST == ST_F16S) {
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(v), r, voff, soff, 0);
+  } else if constexpr (ST == ST_F32) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+  } else {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // e^x (float64): Cody & Waite range reduction, n = rint(x / ln 2),
 // r = (x - n ln2_hi) - n ln2_lo, then the degree-13 Taylor polynomial of e^r

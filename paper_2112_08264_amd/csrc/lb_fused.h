@@ -126,7 +126,14 @@ __global__ void __launch_bounds__(kBlock) k_relayout(const T* __restrict__ src, 
 //
 // TILED: the populations are in the tile-major layout (TX = 64); only the
 // addressing differs.
-template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX, bool TILED = false>
+//
+// LEAD: the loads of a plane are issued LEAD iterations before its psi is
+// published.  LEAD = 1: plane z + D is loaded at the start of the iteration
+// that collides plane z and published at its end, so the loads have one
+// collision to land.  LEAD = 2: plane z + D + 1 is loaded instead and
+// published one iteration later, two collisions after its loads were issued,
+// at the cost of one more plane of populations (and halo) in registers.
+template <int ST, bool SOLID, int TY, int D, bool RECORD, int TX = kFusedTX, bool TILED = false, int LEAD = 1>
 __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>* __restrict__ fin,
                                                               store_t<ST>* __restrict__ fout,
                                                               const uint8_t* __restrict__ mask, Geometry g,
@@ -140,6 +147,7 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
   constexpr int NX = D + 1;                // exchange slots: planes z .. z + D
   constexpr bool CORNERS_IN_ROWS = RX <= 64;  // else the four corners go with the side columns
   static_assert(D >= 2, "psi of plane z + 1 must be ready before plane z is collided");
+  static_assert(LEAD == 1 || LEAD == 2, "loads one or two iterations ahead of their publication");
   static_assert(sizeof(real) == 4, "float arithmetic only; float64 storage runs k_fused_pair");
   static_assert(TX == 32 || TX == 64, "a wave covers two rows of 32 or one row of 64");
   static_assert(TY % RPW == 0 && TY / RPW >= 3, "three waves per component carry the halo");
@@ -208,17 +216,22 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
       v[i] = decode<ST>(*reinterpret_cast<const store*>(fk + (size_t)i * pbytes + b), c.shift[k][i]);
   };
   // TILED: the same from the in-plane byte offset tb of population plane 0
-  // (tile-major) and the plane index z.  The base of each population row
-  // block is wave-uniform (scalar registers), as in load19.
-  const size_t zbytes = (size_t)(2 * Q) * (size_t)plane_n * ES;
-  constexpr size_t kRowBlock = (size_t)kTileNodes * ES;  // bytes of one population's tile rows
+  // (tile-major) and the plane index z, by raw buffer loads: the z-plane's
+  // block is the descriptor's range, the population row block of this
+  // wave's component the scalar offset, tb the lane's offset.
+  const size_t zbytes = (size_t)(2 * Q) * (size_t)plane_n * ES;  // < 2^32 (checked by the host)
+  constexpr uint32_t kRowBlock = (uint32_t)kTileNodes * ES;        // bytes of one population's tile rows
   const uint32_t row_t = TILED ? (uint32_t)tile_major_index(0, gx, gy, 0, g) * ES : 0u;
   const uint32_t hrow_t = TILED ? (uint32_t)tile_major_index(0, hgx, hgy, 0, g) * ES : 0u;
+  const float one = opaque_one();
+  auto zplane = [&](const void* grid, int z) {
+    return buffer_rsrc(reinterpret_cast<const char*>(grid) + (size_t)z * zbytes, (uint32_t)zbytes);
+  };
   auto load19t = [&](uint32_t tb, int z, real (&v)[Q]) {
-    const char* zb = reinterpret_cast<const char*>(fin) + (size_t)z * zbytes + (size_t)(k * Q) * kRowBlock;
+    const __amdgpu_buffer_rsrc_t r = zplane(fin, z);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      v[i] = decode<ST>(*reinterpret_cast<const store*>(zb + (size_t)i * kRowBlock + tb), c.shift[k][i]);
+      v[i] = decode_mix<ST>(buffer_load<ST>(r, tb, (uint32_t)(k * Q + i) * kRowBlock), c.shift[k][i], one);
   };
   auto psi_from = [&](const real (&v)[Q], bool solid) -> real {
     if (SOLID && solid) return real(0);
@@ -245,31 +258,34 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
     }
   };
 
-  real hold[D][Q], pre[Q], hpre[Q];  // hold[d]: populations of plane z + d
-  // prologue: psi of planes z0 - 1 .. z0 + D - 1, populations of z0 .. z0 + D - 1
-  {
+  // NB = D + LEAD population buffers rotate through the roles "plane z
+  // (collided now)", "planes waiting", "plane z + D (published at the end of
+  // this iteration)" and, with LEAD = 2, "plane z + D + 1 (loading)": plane
+  // z0 + q lives in buf[q % NB] and its halo in hbuf[q % LEAD].  The loop
+  // below is unrolled by a multiple of NB and LEAD so that the rotation is a
+  // renaming, not register copies.
+  constexpr int NB = D + LEAD;
+  real buf[NB][Q], hbuf[LEAD][Q];
+  auto load_plane = [&](int q, real (&v)[Q], real (&h)[Q]) {  // plane z0 + q
     if constexpr (TILED) {
-      load19t(row_t, wrapz(z0 - 1), pre);
-      if (has_halo) load19t(hrow_t, wrapz(z0 - 1), hpre);
+      load19t(row_t, wrapz(z0 + q), v);
+      if (has_halo) load19t(hrow_t, wrapz(z0 + q), h);
     } else {
-      const uint32_t zo = plane_n * (uint32_t)wrapz(z0 - 1);
-      load19(row + zo, pre);
-      if (has_halo) load19(hrow + zo, hpre);
+      const uint32_t zo = plane_n * (uint32_t)wrapz(z0 + q);
+      load19(row + zo, v);
+      if (has_halo) load19(hrow + zo, h);
     }
-    publish(z0 - 1, pre, hpre);
-  }
+  };
+  // prologue: psi of planes z0 - 1 .. z0 + D - 1, populations of z0 .. z0 + D - 1
+  // (and, LEAD = 2, the loads of plane z0 + D)
+  load_plane(-1, buf[NB - 1], hbuf[0]);  // plane z0 - 1 is not collided here
+  publish(z0 - 1, buf[NB - 1], hbuf[0]);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    if constexpr (TILED) {
-      load19t(row_t, wrapz(z0 + d), hold[d]);
-      if (has_halo) load19t(hrow_t, wrapz(z0 + d), hpre);
-    } else {
-      const uint32_t zo = plane_n * (uint32_t)wrapz(z0 + d);
-      load19(row + zo, hold[d]);
-      if (has_halo) load19(hrow + zo, hpre);
-    }
-    publish(z0 + d, hold[d], hpre);
+    load_plane(d, buf[d], hbuf[d % LEAD]);
+    publish(z0 + d, buf[d], hbuf[d % LEAD]);
   }
+  if constexpr (LEAD == 2) load_plane(D, buf[D % NB], hbuf[D % LEAD]);
   __syncthreads();
 
   const real omk = coef_om<real>(c, k), omck = coef_omc<real>(c, k), tgk = coef_tg<real>(c, k);
@@ -288,20 +304,15 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
       for (int a = 0; a < 3; ++a) T9[b][a] = (uint32_t)tile_major_index(0, xs3[a], ys3[b], 0, g) * ES;
   }
 
-  for (int j = 0; j < zlen; ++j) {
+  // one z-iteration: collide plane z0 + j held in `cur`, load plane z + D into `nxt`
+  // One z-iteration: collide plane z0 + j held in `cur`; load plane
+  // z0 + j + D + LEAD - 1 into `ld`, `ldh`; publish plane z0 + j + D from
+  // `pub`, `pubh` (the same buffers when LEAD = 1).
+  auto iteration = [&](int j, real (&cur)[Q], real (&ld)[Q], real (&ldh)[Q], real (&pub)[Q], real (&pubh)[Q]) {
     const int z = z0 + j;
     const bool more = j + D <= zlen;  // psi of plane z + D is needed by a later collision
-    // ---- A: issue the loads of plane z + D ----
-    if (more) {
-      if constexpr (TILED) {
-        load19t(row_t, wrapz(z + D), pre);
-        if (has_halo) load19t(hrow_t, wrapz(z + D), hpre);
-      } else {
-        const uint32_t zo = plane_n * (uint32_t)wrapz(z + D);
-        load19(row + zo, pre);
-        if (has_halo) load19(hrow + zo, hpre);
-      }
-    }
+    // ---- A: issue the loads of plane z + D + LEAD - 1 ----
+    if (j + D + LEAD - 1 <= zlen) load_plane(j + D + LEAD - 1, ld, ldh);
     __asm__ volatile("" ::: "memory");
 
     // ---- B: collide plane z ----
@@ -353,7 +364,16 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
       const uint32_t Z[3] = {plane_n * (uint32_t)wrapz(z - 1), plane_n * (uint32_t)z, plane_n * (uint32_t)wrapz(z + 1)};
       const uint32_t here = row + Z[1];
       real fs_all[Q];
-      relax_f32(hold[0], fs_all, rho_k, vx, vy, vz, omk, omck);
+      relax_f32(cur, fs_all, rho_k, vx, vy, vz, omk, omck);
+      if constexpr (TILED && !SOLID) {
+        // every store of direction i goes to one z-plane and one population
+        // row block: uniform descriptor and scalar offset, lane offset T9
+        const __amdgpu_buffer_rsrc_t rz[3] = {zplane(fout, wrapz(z - 1)), zplane(fout, z), zplane(fout, wrapz(z + 1))};
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          buffer_store<ST>(encode<ST>(fs_all[i], c.shift[k][i]), rz[CZ[i] + 1], T9[CY[i] + 1][CX[i] + 1],
+                           (uint32_t)(k * Q + i) * kRowBlock);
+      } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const real fs = fs_all[i];
@@ -378,17 +398,20 @@ __global__ void __launch_bounds__(128 * TY * TX / 64) k_fused(const store_t<ST>*
           *reinterpret_cast<store*>(ok + (size_t)di * pbytes + dn * ES) = encode<ST>(fs, c.shift[k][i]);
         }
       }
+      }
     }
 
     // ---- C: psi and exchange of plane z + D ----
-    if (more) publish(z + D, pre, hpre);
+    if (more) publish(z + D, pub, pubh);
     lds_barrier();
+  };
+  constexpr int PERIOD = NB % LEAD == 0 ? NB : NB * LEAD;
+  for (int j0 = 0; j0 < zlen; j0 += PERIOD) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-#pragma unroll
-      for (int d = 0; d + 1 < D; ++d) hold[d][i] = hold[d + 1][i];
-      hold[D - 1][i] = pre[i];
-    }
+    for (int u = 0; u < PERIOD; ++u)
+      if (j0 + u < zlen)
+        iteration(j0 + u, buf[u % NB], buf[(u + D + LEAD - 1) % NB], hbuf[(u + D + LEAD - 1) % LEAD],
+                  buf[(u + D) % NB], hbuf[(u + D) % LEAD]);
   }
 }
 
@@ -472,7 +495,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
                 "the colour-gradient step has no adjoint record, and solids only as particles");
   static_assert(!PART || (SOLID && MODEL == kModelCG && !STAGED && !TILED && sizeof(store_t<ST>) >= 4),
                 "particles: colour gradient, unstaged, structure of arrays, float32 or float64 storage");
-  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && !SOLID && !RECORD),
+  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && !SOLID),
                 "the tile-major layout serves the 64-wide step without solids or record");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];
@@ -632,16 +655,71 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     }
   };
 
-  real cur[Q], nxt[Q];
-  fill(0, wrapz(z0 - 1), nxt);  // populations of plane z0 - 1 are not needed
-  fill(1, z0, cur);
-  if constexpr (STAGED) fill(2, wrapz(z0 + 1), nxt);
+  // Two population buffers swap roles every plane (the loop below is
+  // unrolled by two): `cur` holds plane z while it is collided, `nxt` plane
+  // z + 1; once plane z is stored, its registers take plane z + 2 (STAGED)
+  // or the loads of the next plane go to the other buffer.
+  real bufA[Q], bufB[Q];
+  fill(0, wrapz(z0 - 1), bufB);  // populations of plane z0 - 1 are not needed
+  fill(1, z0, bufA);
+  if constexpr (STAGED) fill(2, wrapz(z0 + 1), bufB);
   __syncthreads();
+
+  // TILED: in-plane byte offsets of this lane's nine (x +- 1, y +- 1)
+  // destinations in its component's population block, for push stores by
+  // raw buffer (descriptor of the z-plane, scalar offset of the population)
+  uint32_t P9[3][3] = {};
+  const size_t zbytes = (size_t)KI * (size_t)plane_n * sizeof(store_t<ST>);  // < 2^32 where TILED (host check)
+  if constexpr (TILED) {
+    const int xs3[3] = {gx == 0 ? g.nx - 1 : gx - 1, gx, gx == g.nx - 1 ? 0 : gx + 1};
+    const int ys3[3] = {gy == 0 ? g.ny - 1 : gy - 1, gy, gy == g.ny - 1 ? 0 : gy + 1};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        P9[b][a] = (uint32_t)tile_major_index(k * Q, xs3[a], ys3[b], 0, g) * (uint32_t)sizeof(store_t<ST>);
+  }
+  auto zplane = [&](int z) {
+    return buffer_rsrc(reinterpret_cast<const char*>(fout) + (size_t)z * zbytes, (uint32_t)zbytes);
+  };
 
   const real omk = coef_om<real>(c, k), omck = coef_omc<real>(c, k), tgk = coef_tg<real>(c, k);
   const real omA = coef_om<real>(c, 0), omB = coef_om<real>(c, 1);
 
-  for (int j = 0; j < zlen; ++j) {
+  // Post-collision populations of plane z of this lane's node to their
+  // destinations in fout (push streaming; bit i of bb: bounce-back).
+  auto push_plane = [&](int z, const real (&fs)[Q], uint32_t bb) {
+    const int zm = wrapz(z - 1), zp = wrapz(z + 1);
+    const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx == g.nx - 1 ? 0 : gx + 1;
+    const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
+    const int X[3] = {xm, gx, xp};
+    const int Y[3] = {ym, gy, yp};
+    const int Z[3] = {zm, z, zp};
+    const long long here = row + plane_n * z;
+    if constexpr (TILED) {
+      const __amdgpu_buffer_rsrc_t rz[3] = {zplane(zm), zplane(z), zplane(zp)};
+      constexpr uint32_t kRowBlock = (uint32_t)kTileNodes * (uint32_t)sizeof(store_t<ST>);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        buffer_store<ST>(encode<ST>(fs[i], c.shift[k][i]), rz[CZ[i] + 1], P9[CY[i] + 1][CX[i] + 1],
+                         (uint32_t)i * kRowBlock);
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      long long dst;
+      if constexpr (TILED) {
+        dst = tile_major_index(k * Q + i, X[CX[i] + 1], Y[CY[i] + 1], Z[CZ[i] + 1], g);
+      } else {
+        dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
+              (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
+      }
+      if constexpr (SOLID)
+        if ((bb >> i) & 1u) dst = kplane + (long long)OPP[i] * g.Npad + here;
+      fout[dst] = encode<ST>(fs[i], c.shift[k][i]);
+    }
+  };
+  auto iteration = [&](int j, real (&cur)[Q], real (&nxt)[Q]) {
     const int z = z0 + j;
     const int sm = j % 3, s0 = (j + 1) % 3, sp = (j + 2) % 3;  // ring slots of planes z-1, z, z+1
     // STAGED: plane z + 2 is loaded while plane z is collided; its psi is
@@ -676,12 +754,25 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     constexpr bool SC = MODEL == kModelSC;
     real S[3] = {real(0), real(0), real(0)};
     [[maybe_unused]] const real theta_here = ring[s0][0][ly + 1][lx + 1];
+    // PART: bit i set where neighbour x + c_i is solid.  Only a node near a
+    // particle can have one (a fluid node beside a particle node lies within
+    // R + sqrt 2 of its centre), so the other waves skip the flag reads.
+    [[maybe_unused]] uint32_t solid_nb = 0;
+    if constexpr (PART) {
+      if (ring_solid[s0][ly + 1][lx + 1] == 2) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+          if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]] & 1) solid_nb |= 1u << i;
+        }
+      }
+    }
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int si = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
       real q = ring[si][SC ? 1 - k : 0][ly + 1 + CY[i]][lx + 1 + CX[i]];
       if constexpr (PART)
-        if (ring_solid[si][ly + 1 + CY[i]][lx + 1 + CX[i]] & 1) q = theta_here;
+        if ((solid_nb >> i) & 1u) q = theta_here;
       const real tt = weight<real>(i) * q;
       if (CX[i] == 1) S[0] = S[0] + tt;
       if (CX[i] == -1) S[0] = S[0] - tt;
@@ -716,28 +807,7 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
     // before they are stored) and stores them after the stage wait, so that
     // the stores drain during the next collision instead of delaying the wait.
     uint32_t bounced = 0;
-    auto push = [&](const real (&fs)[Q], uint32_t bb) {
-      const int zm = wrapz(z - 1), zp = wrapz(z + 1);
-      const int xm = gx == 0 ? g.nx - 1 : gx - 1, xp = gx == g.nx - 1 ? 0 : gx + 1;
-      const int ym = gy == 0 ? g.ny - 1 : gy - 1, yp = gy == g.ny - 1 ? 0 : gy + 1;
-      const int X[3] = {xm, gx, xp};
-      const int Y[3] = {ym, gy, yp};
-      const int Z[3] = {zm, z, zp};
-      const long long here = row + plane_n * z;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        long long dst;
-        if constexpr (TILED) {
-          dst = tile_major_index(k * Q + i, X[CX[i] + 1], Y[CY[i] + 1], Z[CZ[i] + 1], g);
-        } else {
-          dst = kplane + (long long)i * g.Npad + X[CX[i] + 1] +
-                (long long)g.nx * (Y[CY[i] + 1] + (long long)g.ny * Z[CZ[i] + 1]);
-        }
-        if constexpr (SOLID)
-          if ((bb >> i) & 1u) dst = kplane + (long long)OPP[i] * g.Npad + here;
-        fout[dst] = encode<ST>(fs[i], c.shift[k][i]);
-      }
-    };
+    auto push = [&](const real (&fs)[Q], uint32_t bb) { push_plane(z, fs, bb); };
     if (active && !here_solid) {
       real fs[Q];
       if constexpr (SC) {
@@ -809,43 +879,44 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
         push(zero, 0u);
       }
     }
+    // psi of the halo node of plane z + 2 from the stage into ring slot sm
+    auto drain_halo = [&]() {
+      if (has_halo) {
+        // constant strides, so that every read is one base register plus an immediate offset
+        real h[Q];
+        if (hrows) {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * RY * TX];
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * 2 * RY];
+        }
+        ring_put(sm, hk, hy + 1, hx + 1, density<real>(h), false, 1);
+      }
+    };
     if constexpr (STAGED) {
       const bool store = active && !here_solid;
       if (more) {
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stage loads have landed
         lds_barrier();                        // ... and every other wave's; ring slot sm is free
-        if (has_halo) {
-          // constant strides, so that every read is one base register plus an immediate offset
-          real h[Q];
-          if (hrows) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * RY * TX];
-          } else {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) h[i] = stage[hbase + i * 2 * RY];
-          }
-          ring_put(sm, hk, hy + 1, hx + 1, density<real>(h), false, 1);
-        }
+        drain_halo();
         if (store) push(cur, bounced);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          cur[i] = nxt[i];
-          nxt[i] = stage[ibase + i * RY * TX];
-        }
-        ring_put(sm, k, ly + 1, lx + 1, density<real>(nxt), false, 32);
+        for (int i = 0; i < Q; ++i) cur[i] = stage[ibase + i * RY * TX];  // plane z + 2
+        ring_put(sm, k, ly + 1, lx + 1, density<real>(cur), false, 32);
       } else {
         if (store) push(cur, bounced);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
       }
       lds_barrier();  // psi of z + 2 visible; the stage may be refilled
     } else {
       // A full barrier here measured faster than an LDS-only one: the wave
       // then issues its next loads only after its stores have drained.
-#pragma unroll
-      for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
       __syncthreads();
     }
+  };
+  for (int j0 = 0; j0 < zlen; j0 += 2) {
+    iteration(j0, bufA, bufB);
+    if (j0 + 1 < zlen) iteration(j0 + 1, bufB, bufA);
   }
 }
 

@@ -216,17 +216,23 @@ def test_conservation_on_gpu_over_many_steps():
     assert max(abs(v) for v in t1[2:]) / (t0[0] + t0[1]) < 1e-12
 
 
+# The density target of the reduced storages is max |drho| <= 1e-3 against
+# the float64 oracle.  On the 32^3 demixing workload float32 meets it with a
+# wide margin after 100 steps; float16-shifted meets it after 10 steps and
+# not after 100 (the quench amplifies its per-step storage error of a few
+# 1e-6 past the target), so the 100-step row holds float16-shifted to the
+# looser bound 2e-3 and says so: that row is not the target.
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("storage,tol_rho", [("f32", 1e-4), ("f16s", 2e-3)])
-def test_reduced_storage_error_against_oracle(storage, tol_rho, kernel):
+@pytest.mark.parametrize("storage,steps,tol_rho", [("f32", 100, 1e-4), ("f16s", 10, 1e-3), ("f16s", 100, 2e-3)])
+def test_reduced_storage_error_against_oracle(storage, steps, tol_rho, kernel):
     w = synth.WORKLOADS["mix32_f64"]
-    _say(f"case {storage} vs oracle on {w.name} (100 steps) kernel={kernel}")
+    _say(f"case {storage} vs oracle on {w.name} ({steps} steps) kernel={kernel}")
     a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
     p = O.Params(w.tau, w.G)
-    ref = O.step(O.init_equilibrium(a, b), p, n=100)
-    got = run_gpu(w.shape, w.tau, w.G, a, b, 100, storage=storage, kernel=kernel)
+    ref = O.step(O.init_equilibrium(a, b), p, n=steps)
+    got = run_gpu(w.shape, w.tau, w.G, a, b, steps, storage=storage, kernel=kernel)
     drho = max(np.max(np.abs(O.density(got[k]) - O.density(ref[k]))) for k in range(2))
-    _say(f"  max |drho| = {drho:.3e}")
+    _say(f"  max |drho| = {drho:.3e} (bound {tol_rho:.0e})")
     assert drho <= tol_rho
 
 
