@@ -463,14 +463,20 @@ bool use_fused(const lb_ctx* ctx) {
 // Colour-gradient step with moving particles, per step: the pair kernel
 // with the particle coupling (blind push, densities near particles), the
 // link pass with forces and leap-frog, the owner map of the new positions,
-// covering and uncovering.  Structure-of-arrays layout throughout.
+// covering and uncovering.  On the tile-major layout where nx is a multiple
+// of 64 and ny of 4 (every kernel of the step addresses it), else the
+// structure of arrays.
 template <int ST>
 lb_status particle_step_impl(lb_ctx* ctx, int n) {
   if constexpr (ST == ST_F16S) {
     return LB_EINVAL;  // lb_set_particles admits float64 and float32 storage only
   } else {
     using store = typename StorageTraits<ST>::store_t;
-    lb_status st = set_layout(ctx, false);
+    // the tile-major layout where the plain steps use it (64 x 4 tiles)
+    const bool tiled = ctx->p.nx % kTileX == 0 && ctx->p.ny % kTileY == 0 &&
+                       2.0 * Q * ctx->g.nx * ctx->g.ny * ctx->elem < 4294967296.0 &&
+                       (ST != ST_F64 || ctx->p.nx % kWideTX == 0);
+    lb_status st = set_layout(ctx, tiled);
     if (st != LB_OK) return st;
     for (int s = 0; s < n; ++s) {
       const store* fin = static_cast<const store*>(ctx->grid[ctx->cur]);
@@ -480,21 +486,37 @@ lb_status particle_step_impl(lb_ctx* ctx, int n) {
       const PartFluid pf{own, ctx->rho_buf};
       st = launch(ctx, SLOT_FUSED, [&] {
         if constexpr (ST == ST_F64) {
-          const FusedTiling t = ctx->tiling;
-          k_fused_pair<ST, true, kFusedTY, false, false, kFusedTX, kModelCG, false, true>
-              <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr,
-                                                                        pf);
+          if (tiled) {
+            const FusedTiling t = ctx->tiling_wide;
+            k_fused_pair<ST, true, kWideTY, false, false, kWideTX, kModelCG, true, true>
+                <<<dim3(t.total), dim3(2 * kWideTX * kWideTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
+                                                                                   nullptr, pf);
+          } else {
+            const FusedTiling t = ctx->tiling;
+            k_fused_pair<ST, true, kFusedTY, false, false, kFusedTX, kModelCG, false, true>
+                <<<dim3(t.total), dim3(64 * kFusedTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t, nullptr,
+                                                                          pf);
+          }
         } else {
           const FusedTiling t = ctx->tiling_cg;
-          k_fused_pair<ST, true, kFloatTY, false, false, kFloatTX, kModelCG, false, true>
-              <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c, t,
-                                                                                   nullptr, pf);
+          if (tiled)
+            k_fused_pair<ST, true, kFloatTY, false, false, kFloatTX, kModelCG, true, true>
+                <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c,
+                                                                                     t, nullptr, pf);
+          else
+            k_fused_pair<ST, true, kFloatTY, false, false, kFloatTX, kModelCG, false, true>
+                <<<dim3(t.total), dim3(2 * kFloatTX * kFloatTY), 0, ctx->stream>>>(fin, fout, nullptr, ctx->g, ctx->c,
+                                                                                     t, nullptr, pf);
         }
       });
       if (st != LB_OK) return st;
       st = launch(ctx, SLOT_PART_FORCE, [&] {
-        kp_force_move<ST, 2><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps, ctx->g,
-                                                                        ctx->c);
+        if (tiled)
+          kp_force_move<ST, 2, true><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps,
+                                                                               ctx->g, ctx->c);
+        else
+          kp_force_move<ST, 2, false><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, ctx->rho_buf, ctx->ps,
+                                                                                ctx->g, ctx->c);
       });
       if (st != LB_OK) return st;
       st = launch(ctx, SLOT_PART_OWNER, [&] {
@@ -503,8 +525,12 @@ lb_status particle_step_impl(lb_ctx* ctx, int n) {
       });
       if (st != LB_OK) return st;
       st = launch(ctx, SLOT_PART_REMAP, [&] {
-        kp_remap<ST, 2><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps, ctx->g,
-                                                                   ctx->c);
+        if (tiled)
+          kp_remap<ST, 2, true><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps,
+                                                                          ctx->g, ctx->c);
+        else
+          kp_remap<ST, 2, false><<<ctx->np, kPartThreads, 0, ctx->stream>>>(fout, own, own_new, ctx->mask, ctx->ps,
+                                                                           ctx->g, ctx->c);
       });
       if (st != LB_OK) return st;
       ctx->cur ^= 1;
@@ -1987,7 +2013,7 @@ lb_status lb_set_particles(lb_ctx* ctx, int32_t count, double radius, double mas
     return LB_EINVAL;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  const lb_status st = set_layout(ctx, false);  // the particle kernels address the structure of arrays
+  const lb_status st = set_layout(ctx, false);  // placing and releasing particles address the structure of arrays
   if (st != LB_OK) return st;
   return set_particles_common<2>(ctx, count, radius, mass, pos, vel, omega,
                                  [ctx](void** ptr, size_t bytes) { return dev_alloc(ctx, ptr, bytes); });

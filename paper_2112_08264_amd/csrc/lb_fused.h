@@ -464,8 +464,9 @@ struct PartFluid {
 // TILED: the populations are in the tile-major layout (64 x 4 tiles, no
 // solids, either model); only the addressing differs.
 //
-// PART (colour gradient with moving particles, structure of arrays,
-// unstaged): the solid nodes are those the owner map gives to a particle.
+// PART (colour gradient with moving particles, unstaged; structure of arrays
+// or, TILED, the tile-major layout): the solid nodes are those the owner map
+// gives to a particle.
 // Neutral wetting: in the phase-field stencil of a fluid node, a neighbour
 // inside a particle contributes the node's own Theta.  Streaming is blind:
 // every fluid node pushes its 19 post-collision populations to x + c_i and
@@ -493,9 +494,9 @@ __global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* _
   static_assert(!(STAGED && SOLID), "lattices with solids run the unstaged kernel");
   static_assert(MODEL == kModelSC || (!RECORD && (!SOLID || PART)),
                 "the colour-gradient step has no adjoint record, and solids only as particles");
-  static_assert(!PART || (SOLID && MODEL == kModelCG && !STAGED && !TILED && sizeof(store_t<ST>) >= 4),
-                "particles: colour gradient, unstaged, structure of arrays, float32 or float64 storage");
-  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && !SOLID),
+  static_assert(!PART || (SOLID && MODEL == kModelCG && !STAGED && sizeof(store_t<ST>) >= 4),
+                "particles: colour gradient, unstaged, float32 or float64 storage");
+  static_assert(!TILED || (TX == kTileX && TY % kTileY == 0 && (!SOLID || PART)),
                 "the tile-major layout serves the 64-wide step without solids or record");
   constexpr int NQ = ((TY + 2) * TX / 2 + 63) / 64;  // 16-byte loads per lane covering one population plane's rows
   __shared__ real ring[3][2][RY][RX];

@@ -63,6 +63,14 @@ struct PartState {
   double rho0[2];  // density of each component at nodes the particles uncover
 };
 
+// Population plane ki of node n = x + nx (y + ny z): structure of arrays, or
+// the tile-major layout of the fused steps (TILED).
+template <bool TILED>
+__device__ __forceinline__ long long pop_index(int ki, int n, int x, int y, int z, const Geometry& g) {
+  if constexpr (TILED) return tile_major_index(ki, x, y, z, g);
+  else return (long long)ki * g.Npad + n;
+}
+
 // Periodic wrap of any coordinate (a box of a particle whose state has gone
 // non-finite still addresses the lattice).
 __device__ __forceinline__ int wrap_coord(int c, int L) {
@@ -214,8 +222,8 @@ __device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6
 //
 // NC components: the populations of component k are planes k Q .. k Q + 18,
 // its recorded densities rho_buf[k N ..]; each link is handled per
-// component, component 0 first.
-template <int ST, int NC = 1>
+// component, component 0 first.  TILED: fnew is in the tile-major layout.
+template <int ST, int NC = 1, bool TILED = false>
 __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __restrict__ fnew,
                                                               const int* __restrict__ owner,
                                                               const double* __restrict__ rho_buf, PartState ps,
@@ -259,7 +267,6 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
       }
 #pragma unroll
       for (int kc = 0; kc < NC; ++kc) {
-        const long long kp = (long long)(kc * Q) * g.Npad;
         real pushed[kLinkChunk];
         double rh[kLinkChunk];
 #pragma unroll
@@ -268,7 +275,7 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
           pushed[k] = real(0);
           rh[k] = 0.0;
           if (outside[k]) {
-            pushed[k] = decode<ST>(fnew[kp + (long long)i * g.Npad + n], c.shift[kc][i]);
+            pushed[k] = decode<ST>(fnew[pop_index<TILED>(kc * Q + i, n, xs, ys, zs, g)], c.shift[kc][i]);
             rh[k] = rho_buf[(long long)kc * g.N + nf[k]];
           }
         }
@@ -280,8 +287,8 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
           double rb[3];
           const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
           const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[kc][i]);  // w_opp(i) = w_i
-          fnew[kp + (long long)OPP[i] * g.Npad + nf[k]] = back;
-          fnew[kp + (long long)i * g.Npad + n] = store_t<ST>(0);
+          fnew[pop_index<TILED>(kc * Q + OPP[i], nf[k], xf, yf, zf, g)] = back;
+          fnew[pop_index<TILED>(kc * Q + i, n, xs, ys, zs, g)] = store_t<ST>(0);
           const double gv = static_cast<double>(decode<ST>(back, c.shift[kc][i]));
           const double t = (gv + gv) + W;
           const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
@@ -371,8 +378,9 @@ __global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ own
 }
 
 // Covering and uncovering after the move; mask follows the new owner map.
-// NC components, each handled in turn at a node, component 0 first.
-template <int ST, int NC = 1>
+// NC components, each handled in turn at a node, component 0 first.  TILED:
+// f is in the tile-major layout.
+template <int ST, int NC = 1, bool TILED = false>
 __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict__ f, const int* __restrict__ owner_old,
                                                          const int* __restrict__ owner_new, uint8_t* __restrict__ mask,
                                                          PartState ps, Geometry g, StepCoeffs c) {
@@ -391,17 +399,18 @@ __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict
     const bool uncovered = owner_old[n] == p && owner_fluid(owner_new[n]);
     if (!covered && !uncovered) continue;
     const double d[3] = {double(cc[0]) - r[0], double(cc[1]) - r[1], double(cc[2]) - r[2]};
+    const int wx = wrap_coord(cc[0], g.nx), wy = wrap_coord(cc[1], g.ny), wz = wrap_coord(cc[2], g.nz);
     mask[n] = covered ? 1 : 0;
 #pragma unroll
     for (int kc = 0; kc < NC; ++kc) {
-      const long long kp = (long long)(kc * Q) * g.Npad;
       real vals[Q];
       double sign;
       if (covered) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          vals[i] = decode<ST>(f[kp + (long long)i * g.Npad + n], c.shift[kc][i]);
-          f[kp + (long long)i * g.Npad + n] = store_t<ST>(0);
+          const long long at = pop_index<TILED>(kc * Q + i, n, wx, wy, wz, g);
+          vals[i] = decode<ST>(f[at], c.shift[kc][i]);
+          f[at] = store_t<ST>(0);
         }
         sign = 1.0;
       } else {
@@ -417,7 +426,7 @@ __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict
           const real cu = cdot<real>(i, ux, uy, uz);
           const real feq = (weight<real>(i) * rho0) * (((real(1) + real(3) * cu) + real(4.5) * cu * cu) - t15);
           const store_t<ST> sv = encode<ST>(feq, c.shift[kc][i]);
-          f[kp + (long long)i * g.Npad + n] = sv;
+          f[pop_index<TILED>(kc * Q + i, n, wx, wy, wz, g)] = sv;
           vals[i] = decode<ST>(sv, c.shift[kc][i]);  // the stored value, so that the exchange is exact
         }
         sign = -1.0;

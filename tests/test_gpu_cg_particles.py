@@ -87,6 +87,11 @@ CASES = {
     # two overlapping spheres: nodes inside both belong to the lower index
     "overlap": ((18, 18, 22), PT.Particles(3.1, 400.0, [[9.3, 8.8, 9.1], [13.4, 9.6, 9.0]],
                                            [[0.02, 0.0, 0.0], [0.02, 0.01, 0.0]], None)),
+    # nx a multiple of 64 and ny of 4: the step runs on the tile-major layout; one sphere straddles the x-edge
+    # of the two 64-wide tiles, one the periodic x boundary, one a 4-row tile edge in y
+    "tiled": ((12, 12, 128), PT.Particles(3.2, 400.0, [[63.6, 5.3, 6.1], [1.2, 7.9, 5.4], [100.3, 4.1, 7.7]],
+                                          [[0.08, -0.03, 0.02], [-0.06, 0.05, 0.0], [0.0, 0.07, -0.05]],
+                                          [[0.01, 0.0, 0.02], [0.0, -0.02, 0.0], [0.02, 0.0, 0.0]])),
 }
 
 
@@ -201,13 +206,14 @@ def test_f64_total_momentum_conserved_with_many_particles():
     assert abs(M1 - M0) <= 1e-3 * M0  # uncovered nodes start at rho0: mass is not conserved exactly
 
 
-def test_f32_against_the_oracle():
+@pytest.mark.parametrize("name", ["two", "tiled"])
+def test_f32_against_the_oracle(name):
     """float32 fluid with float64 particle arithmetic, 15 steps: positions
     within 1e-6 and populations within 1e-5 of the float64 oracle (float32
     rounds each population to 2^-24 relative; forces sum a few hundred links
-    of such values)."""
-    shape, part = CASES["two"]
-    _say(f"case cg particles f32 shape={shape}")
+    of such values).  "tiled" runs on the tile-major layout."""
+    shape, part = CASES[name]
+    _say(f"case cg particles f32 {name} shape={shape}")
     r1, r2, u = _mixture(shape, 68)
     f, owner = CP.init(r1, r2, part, u)
     ref, q, _ = CP.step(f, PAR, part.copy(), owner, n=15)
@@ -323,3 +329,70 @@ def test_full_size_case3_conserves_momentum(name):
     _say(f"  |dP| {drift:.2e} (bound {bound:.2e}), dM/M {abs(M1 - M0) / M0:.2e}")
     assert drift <= bound
     assert np.all((pos >= 0.0) & (pos < 256.0))
+
+
+@pytest.mark.parametrize("name", ["case3cg_c_256_f64", "case3cg_c_256_f32"])
+def test_full_size_case3_sampled_one_step(name):
+    """The 10% workload of the paper's case 3 (2407 spheres in the 256^3
+    two-fluid box, on the tile-major layout) as the benchmark launches it,
+    one step, checked sphere by sphere: 8 sampled isolated spheres against
+    the oracle stepped on a 32^3 window around each (``particle_window``).
+    float64: force and torque within the summation bound of the sphere's link
+    terms, velocities and position within that bound carried through, both
+    components' populations within R + 3 of the centre bit for bit (uncovered
+    nodes to 1e-13).  float32: bounds from its precision, as for the single
+    fluid."""
+    import particle_window as PW
+
+    torch = _torch()
+    w = synth.WORKLOADS[name]
+    _say(f"case {w.name} sampled one step")
+    shape, n = w.shape, w.nodes
+    r1, r2 = synth.colour_fields(shape, w.seed)
+    centres = synth.sphere_centres(shape, w.spheres, w.radius, w.sphere_seed)
+    rng = np.random.default_rng(71)
+    vel = rng.uniform(-0.03, 0.03, (w.spheres, 3))
+    omg = rng.uniform(-0.003, 0.003, (w.spheres, 3))
+    mass = synth.particle_mass(w.radius)
+    p = CP.Params(w.tau, w.sigma, w.beta, w.rho0)
+    sample = PW.isolated(centres, w.radius, shape, 8, 72, margin=7.0)
+    assert sample.size == 8
+    with _lattice(shape, p, w.storage) as lat:
+        lat.set_fields(r1.ravel(), r2.ravel())
+        lat.set_particles(centres, w.radius, mass, vel, omg)
+        lat.step(1)
+        f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+        lat.get_populations(f)
+        pos, v1, w1, force, torque = lat.particles()
+        torch.cuda.synchronize()
+    f = f.view(2, 19, n)
+    errs = []
+    for q in sample:
+        F, T, rr, vr, wr, ref, idx, bd = PW.step_window_cg(r1, r2, p, w.radius, mass, centres[q], vel[q], omg[q],
+                                                          shape)
+        got = f[:, :, torch.from_numpy(idx).to("cuda")].cpu().numpy()
+        if w.storage == "f64":
+            bF, bC = bd["link"], bd["cover"]
+            inertia = 0.4 * mass * w.radius * w.radius
+            assert np.all(np.abs(force[q] - F) <= bF[:3]), q
+            assert np.all(np.abs(torque[q] - T) <= bF[3:]), q
+            assert np.all(np.abs(v1[q] - vr) <= (bF[:3] + bC[:3]) / mass
+                          + 8 * U * (np.abs(vr) + np.abs(F) / mass + np.abs(vel[q]))), q
+            assert np.all(np.abs(w1[q] - wr) <= (bF[3:] + bC[3:]) / inertia
+                          + 8 * U * (np.abs(wr) + np.abs(T) / inertia + np.abs(omg[q]))), q
+            assert np.all(np.abs(pos[q] - rr) <= bF[:3] / mass + 8 * U * (np.abs(rr) + 1.0)), q
+            keep = ~bd["uncovered"]
+            assert np.array_equal(got[:, :, keep], ref[:, :, keep]), q
+            if np.any(bd["uncovered"]):
+                assert O.population_error(got[:, :, ~keep], ref[:, :, ~keep]) <= 1e-13, q
+        else:
+            errs.append([np.max(np.abs(force[q] - F)), np.max(np.abs(torque[q] - T)), np.max(np.abs(pos[q] - rr)),
+                         np.max(np.abs(v1[q] - vr)), np.max(np.abs(w1[q] - wr)), np.max(np.abs(got - ref))])
+    if errs:
+        e = np.max(np.array(errs), axis=0)
+        _say(f"  max |dF| {e[0]:.1e} |dT| {e[1]:.1e} |dpos| {e[2]:.1e} |dv| {e[3]:.1e} |domega| {e[4]:.1e} "
+             f"|df| {e[5]:.1e}")
+        # float32 populations (2^-24 relative of values near w_i) summed over about 2200 links per component
+        assert e[0] <= 2e-4 and e[1] <= 2e-3
+        assert e[2] <= 2e-7 and e[3] <= 2e-7 and e[4] <= 2e-7
+        assert e[5] <= 1e-5

@@ -170,3 +170,34 @@ def test_uncovered_nodes_take_the_stated_densities_and_the_surface_velocity():
     for k in range(2):
         assert np.max(np.abs(f[k][:, fl] - feq[k][:, None])) < 1e-14
     assert np.sum(owner != owner0) > 10
+
+
+def test_window_step_equals_the_whole_lattice_step():
+    """Locality and exact translation of the case-3 step: for spheres far from
+    every other sphere and from the lattice's ends, one oracle step of a 32^3
+    window around the sphere (``particle_window.step_window_cg``) gives the
+    whole-lattice step's force, torque, position, velocities and both
+    components' nearby populations bit for bit (the full-size GPU check relies
+    on this).  96^3, pure colours at random, 30 moving spheres of radius 5.5."""
+    import particle_window as PW
+    L = 96
+    shape = (L, L, L)
+    R = 5.5
+    centres = synth.sphere_centres(shape, 30, R, 4)
+    rng = np.random.default_rng(59)
+    vel = rng.uniform(-0.03, 0.03, (30, 3))
+    omg = rng.uniform(-0.003, 0.003, (30, 3))
+    mass = synth.particle_mass(R)
+    r1, r2 = synth.colour_fields(shape, 12)
+    p = CP.Params((1.0, 1.0), 0.01, 0.7, (0.5, 0.5))
+    part = PT.Particles(R, mass, centres, vel, omg)
+    f, owner = CP.init(r1, r2, part)
+    f1, q, _ = CP.step(f, p, part.copy(), owner, n=1)
+    f1 = f1.reshape(2, 19, -1)
+    sample = PW.isolated(centres, R, shape, 3, 0, margin=7.0)
+    assert sample.size == 3
+    for k in sample:
+        F, T, rr, vr, wr, fw, idx, _ = PW.step_window_cg(r1, r2, p, R, mass, centres[k], vel[k], omg[k], shape)
+        assert np.array_equal(F, q.force[k]) and np.array_equal(T, q.torque[k]), k
+        assert np.array_equal(rr, q.pos[k]) and np.array_equal(vr, q.vel[k]) and np.array_equal(wr, q.omg[k]), k
+        assert np.array_equal(fw, f1[:, :, idx]), k
