@@ -462,7 +462,7 @@ struct PartFluid {
 // ---------------------------------------------------------------------------
 //
 // TILED: the populations are in the tile-major layout (64 x 4 tiles, no
-// solids, either model); only the addressing differs.
+// fixed solids, either model); only the addressing differs.
 //
 // PART (colour gradient with moving particles, unstaged; structure of arrays
 // or, TILED, the tile-major layout): the solid nodes are those the owner map
@@ -474,13 +474,16 @@ struct PartFluid {
 // population sent into a particle waiting in the particle node's slot (and
 // the zero it replaces in the fluid node's).  Fluid nodes near a particle
 // record rho_A and rho_B for that pass.
+//
+// The float32 particle kernel on the tile-major layout is held to 128
+// registers (four waves per SIMD, two workgroups per compute unit); it needs
+// 153 unconstrained, which leaves one workgroup per compute unit.
 template <int ST, bool SOLID, int TY, bool RECORD, bool STAGED, int TX = kFusedTX, int MODEL = kModelSC,
           bool TILED = false, bool PART = false>
-__global__ void __launch_bounds__(2 * TX * TY) k_fused_pair(const store_t<ST>* __restrict__ fin,
-                                                            store_t<ST>* __restrict__ fout,
-                                                            const uint8_t* __restrict__ mask, Geometry g,
-                                                            StepCoeffs c, FusedTiling t,
-                                                            real_t<ST>* __restrict__ rec, PartFluid pf = {}) {
+__global__ void __launch_bounds__(2 * TX * TY, (PART && TILED && sizeof(store_t<ST>) == 4) ? 4 : 1)
+    k_fused_pair(const store_t<ST>* __restrict__ fin, store_t<ST>* __restrict__ fout,
+                 const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c, FusedTiling t,
+                 real_t<ST>* __restrict__ rec, PartFluid pf = {}) {
   using real = real_t<ST>;
   constexpr int WPR = TX / 32;  // waves per tile row
   constexpr int NW = TY * WPR;  // waves per workgroup

@@ -462,14 +462,17 @@ def test_f64_tile_major_step_bitwise_equal_to_oracle(shape):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 @pytest.mark.parametrize("shape,with_solid", [((5, 8, 64), False), ((3, 12, 128), False), ((70, 4, 64), False),
-                                              ((6, 8, 64), True)])
+                                              ((6, 8, 64), True), ((40, 16, 192), False), ((9, 8, 64), False),
+                                              ((70, 24, 128), False)])
 def test_float_tile_major_step_equals_the_structure_of_arrays_step(shape, with_solid, storage):
     """Float storage runs on the tile-major layout where nx is a multiple of 64
     and ny of 4.  lb_step_between steps snapshots, which are in the
     structure-of-arrays layout, with the structure-of-arrays kernel; the node
     arithmetic does not depend on the layout, so three steps each way give
     the same populations bit for bit (with totals and a population read
-    between the tile-major steps)."""
+    between the tile-major steps).  Shapes: one tile (x and y wrap onto the
+    tile itself), three tiles in x, 64 x 8 tiles in several z-chunks with a
+    ragged last chunk."""
     torch = _torch()
     n = int(np.prod(shape))
     _say(f"case {storage} tile-major vs structure of arrays shape={shape} solid={with_solid}")
@@ -517,3 +520,29 @@ def test_f64_kernel_switches_between_layouts_bitwise():
         lat.get_populations(f)
         torch.cuda.synchronize()
     assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)), O.step(O.init_equilibrium(a, b), p, n=5))
+
+
+@pytest.mark.parametrize("storage", ["f16s", "f32"])
+def test_full_size_tile_major_step_equals_the_structure_of_arrays_step(storage):
+    """The 256^3 spinodal workload as the benchmark launches it (float16-shifted:
+    64 x 8 tiles in 128-plane chunks; float32: 64 x 4 tiles, loads two planes
+    ahead) against the structure-of-arrays kernel, two steps each way from
+    the same state: the same populations bit for bit."""
+    torch = _torch()
+    w = synth.WORKLOADS["spinodal256_f64"]
+    _say(f"case {storage} full size tile-major vs structure of arrays shape={w.shape}")
+    a, b = synth.fluid_fields(w.shape, w.amp, w.seed)
+    with P.Lattice(w.shape, tau=w.tau, G=w.G, storage=storage) as lat:
+        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
+        nb = P.lb_state_bytes(lat.ctx)
+        snaps = [torch.empty(nb, dtype=torch.uint8, device="cuda") for _ in range(2)]
+        P.lb_save_state(lat.ctx, snaps[0])
+        P.lb_step_between(lat.ctx, snaps[0], snaps[1])
+        P.lb_step_between(lat.ctx, snaps[1], snaps[0])
+        lat.step(2)
+        mine = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        P.lb_save_state(lat.ctx, mine)
+        torch.cuda.synchronize()
+        assert torch.equal(mine, snaps[0])
+        (_, _, _, _, _), nonfinite = lat.totals()
+        assert not nonfinite
