@@ -104,6 +104,21 @@ __device__ __forceinline__ float opaque_one() {
   return one;
 }
 
+// The value held by lane l ^ 32, the same node's other component in the
+// component-pair kernels: one v_permlane32_swap per 32-bit word (lanes 32-63
+// of the first operand trade places with lanes 0-31 of the second), in
+// place of an LDS permute.
+__device__ __forceinline__ uint32_t other_half_u32(uint32_t x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (__lane_id() & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float other_half(float v) { return __uint_as_float(other_half_u32(__float_as_uint(v))); }
+__device__ __forceinline__ double other_half(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const uint32_t lo = other_half_u32((uint32_t)b), hi = other_half_u32((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // `decode` for a uniform shift, with `one` from opaque_one().
 template <int ST>
 __device__ __forceinline__ typename StorageTraits<ST>::real decode_mix(typename StorageTraits<ST>::store_t v,

@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(2 * TX * TY, (PART && TILED && sizeof(store_t<
     if constexpr (MODEL == kModelSC) {
       ring[s][kk][y][x] = (SOLID && solid) ? real(0) : pseudopotential(rho, coef_ref<real>(c));
     } else {
-      const real o = __shfl_xor(rho, pm, 64);
+      const real o = pm == 32 ? other_half(rho) : __shfl_xor(rho, pm, 64);
       if (kk == 0) ring[s][0][y][x] = (SOLID && solid) ? real(0) : (rho - o) / (rho + o);
     }
   };
@@ -740,10 +740,10 @@ __global__ void __launch_bounds__(2 * TX * TY, (PART && TILED && sizeof(store_t<
     if constexpr (SOLID) here_solid = (ring_solid[s0][ly + 1][lx + 1] & 1) != 0;
     const real rho_k = density<real>(cur);
     real m_k[3] = {lattice_sum<0, 0, real>(cur), lattice_sum<1, 0, real>(cur), lattice_sum<2, 0, real>(cur)};
-    const real rho_o = __shfl_xor(rho_k, 32, 64);
+    const real rho_o = other_half(rho_k);
     real m_o[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) m_o[a] = __shfl_xor(m_k[a], 32, 64);
+    for (int a = 0; a < 3; ++a) m_o[a] = other_half(m_k[a]);
     const real rhoA = k == 0 ? rho_k : rho_o, rhoB = k == 0 ? rho_o : rho_k;
     const real den = omA * rhoA + omB * rhoB;
     real up[3];
@@ -833,26 +833,51 @@ __global__ void __launch_bounds__(2 * TX * TY, (PART && TILED && sizeof(store_t<
         // between the components by the recolouring.  The partner lane
         // (lane ^ 32, same node, other component) is active exactly when
         // this lane is, so the exchanges below are complete.
+        //
+        // float64 keeps the oracle's operations (and so its bits).  float
+        // arithmetic takes hardware reciprocals and square root (about 1 ulp)
+        // and multiplies by them: three reciprocals per node instead of 28
+        // correctly rounded quotients, most of this step's vector ALU work.
+        constexpr bool F32 = sizeof(real) == 4;
         const real rho = rhoA + rhoB;
+        [[maybe_unused]] real inv_rho = real(0);
+        if constexpr (F32) inv_rho = __builtin_amdgcn_rcpf(rho);
         real u[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const real mA = k == 0 ? m_k[a] : m_o[a], mB = k == 0 ? m_o[a] : m_k[a];
-          u[a] = (mA + mB) / rho;
+          if constexpr (F32) u[a] = (mA + mB) * inv_rho;
+          else u[a] = (mA + mB) / rho;
         }
         const real g3[3] = {real(3) * S[0], real(3) * S[1], real(3) * S[2]};
         const real gg = (g3[0] * g3[0] + g3[1] * g3[1]) + g3[2] * g3[2];
         const bool iface = gg > cg_interface_g2<real>();
-        const real gn = iface ? real(sqrt(gg)) : real(0);
-        real nv[3];
+        real gn = real(0), nv[3];
+        if constexpr (F32) {
+          gn = iface ? __builtin_amdgcn_sqrtf(gg) : real(0);
+          const real inv_gn = iface ? __builtin_amdgcn_rcpf(gn) : real(0);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) nv[a] = iface ? g3[a] / gn : real(0);
-        const real inv_nubar = (rhoA / rho) * coef_cg_inv_nu<real>(c, 0) + (rhoB / rho) * coef_cg_inv_nu<real>(c, 1);
-        const real nubar = real(1) / inv_nubar;
-        const real om = real(2) / (real(6) * nubar + real(1));
+          for (int a = 0; a < 3; ++a) nv[a] = g3[a] * inv_gn;
+        } else {
+          gn = iface ? real(sqrt(gg)) : real(0);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) nv[a] = iface ? g3[a] / gn : real(0);
+        }
+        real om, r, ck;
+        if constexpr (F32) {
+          // omega = 2 / (6 nubar + 1) = 2 (1/nubar) / (6 + 1/nubar)
+          const real inv_nubar = (rhoA * inv_rho) * coef_cg_inv_nu<real>(c, 0) + (rhoB * inv_rho) * coef_cg_inv_nu<real>(c, 1);
+          om = (real(2) * inv_nubar) * __builtin_amdgcn_rcpf(real(6) + inv_nubar);
+          r = (coef_cg_beta<real>(c) * (rhoA * rhoB)) * (inv_rho * inv_rho);
+          ck = rho_k * inv_rho;
+        } else {
+          const real inv_nubar = (rhoA / rho) * coef_cg_inv_nu<real>(c, 0) + (rhoB / rho) * coef_cg_inv_nu<real>(c, 1);
+          const real nubar = real(1) / inv_nubar;
+          om = real(2) / (real(6) * nubar + real(1));
+          r = (coef_cg_beta<real>(c) * (rhoA * rhoB)) / (rho * rho);
+          ck = rho_k / rho;
+        }
         const real pcoef = (real(0.5) * (coef_cg_s225<real>(c) * om)) * gn;
-        const real r = (coef_cg_beta<real>(c) * (rhoA * rhoB)) / (rho * rho);
-        const real ck = rho_k / rho;
         const real uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
         const real t15u = real(1.5) * uu;
 #pragma unroll
@@ -862,9 +887,10 @@ __global__ void __launch_bounds__(2 * TX * TY, (PART && TILED && sizeof(store_t<
           const real cn = cdot<real>(i, nv[0], nv[1], nv[2]);
           const real pert = pcoef * (weight<real>(i) * (cn * cn) - cg_b<real>(i));
           const real fk = (cur[i] + om * (feq - cur[i])) + pert;
-          const real fo = __shfl_xor(fk, 32, 64);
+          const real fo = other_half(fk);
           const real fstar = k == 0 ? fk + fo : fo + fk;
-          const real t = (r * (cn / cg_clen<real>(i))) * (weight<real>(i) * rho);
+          const real cosphi = F32 ? cn * (real(1) / cg_clen<real>(i)) : cn / cg_clen<real>(i);
+          const real t = (r * cosphi) * (weight<real>(i) * rho);
           fs[i] = k == 0 ? ck * fstar + t : ck * fstar - t;
         }
       }
