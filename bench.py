@@ -60,8 +60,8 @@ def log(msg: str) -> None:
 def time_form(P, torch, w, storage: str, steps: int, warmup: int, fields, kernel="auto", timing_slots=True,
               solid=None, repeats=0, repeat_steps=300):
     """Run one storage form; return a dict of timings.  The starting totals
-    are read before the warmup: a read puts the state back in the structure-
-    of-arrays order, and the reorder into the step's own order then falls in
+    are read before the warmup: the state is then still in the structure-
+    of-arrays order of lb_set_fields, and the reorder into the step's own order falls in
     the warmup, not in the timed steps.  ``repeats`` more blocks of
     ``repeat_steps`` steps follow the timed region, each timed on its own."""
     a, b = fields

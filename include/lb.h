@@ -112,13 +112,15 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b,
  * solid neighbours.  Enqueued; returns before completion.
  * Where nx is a multiple of 64 and ny of 4, the fused steps keep the
  * populations in a tile-major order inside the library (one contiguous
- * block per 64 x 4 tile and plane; float64 without solid nodes, float
- * storage with or without): the first step after lb_set_fields,
- * lb_set_populations, lb_restore_state or a call that reads the state
- * (lb_moments, lb_get_populations, lb_totals, lb_save_state to host memory,
- * the two-pass kernel) reorders the grid once, and those calls reorder it
- * back (one read and one write of the grid each).  Results do not depend on
- * the order.  Errors: LB_EINVAL (n < 0), LB_ESTATE (no lb_set_fields /
+ * block per 64 x 4 tile and plane; float64 without fixed solid nodes,
+ * float storage with or without, and the steps with moving particles):
+ * the first step after lb_set_fields, lb_set_populations,
+ * lb_restore_state, lb_set_particles or a call that needs the structure of
+ * arrays (lb_get_populations, lb_save_state to host memory, the two-pass
+ * kernel) reorders the grid once, and those calls reorder it back (one
+ * read and one write of the grid each).  lb_moments and lb_totals read
+ * either order and reorder nothing.  Results do not depend on the order.
+ * Errors: LB_EINVAL (n < 0), LB_ESTATE (no lb_set_fields /
  * lb_set_populations yet), LB_EDEVICE. */
 lb_status lb_step(lb_ctx* ctx, int32_t n);
 

@@ -622,12 +622,23 @@ lb_status moments_impl(lb_ctx* ctx, double* ra, double* rb, double* u) {
     c.G = 0.0;
     c.Gf = 0.0f;
   }
+  // the state is read in whichever layout the steps left it
   if (mask_or_null(ctx) != nullptr) {
-    k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, c);
-    k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, c);
+    if (ctx->tiled) {
+      k_psi<ST, true, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, c);
+      k_moments<ST, true, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, c);
+    } else {
+      k_psi<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ctx->g, c);
+      k_moments<ST, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, ctx->mask, ra, rb, u, ctx->g, c);
+    }
   } else {
-    k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, c);
-    k_moments<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, c);
+    if (ctx->tiled) {
+      k_psi<ST, false, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, c);
+      k_moments<ST, false, true><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, c);
+    } else {
+      k_psi<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ctx->g, c);
+      k_moments<ST, false><<<nb, kBlock, 0, ctx->stream>>>(f, psi, nullptr, ra, rb, u, ctx->g, c);
+    }
   }
   LB_HIP(hipGetLastError());
   return LB_OK;
@@ -636,8 +647,12 @@ lb_status moments_impl(lb_ctx* ctx, double* ra, double* rb, double* u) {
 template <int ST>
 lb_status totals_impl(lb_ctx* ctx, int blocks) {
   using store = typename StorageTraits<ST>::store_t;
-  k_totals_partial<ST><<<blocks, kBlock, 0, ctx->stream>>>(static_cast<const store*>(ctx->grid[ctx->cur]),
-                                                          mask_or_null(ctx), ctx->g, ctx->c, ctx->partial);
+  if (ctx->tiled)  // the state is read in whichever layout the steps left it
+    k_totals_partial<ST, 2, true><<<blocks, kBlock, 0, ctx->stream>>>(static_cast<const store*>(ctx->grid[ctx->cur]),
+                                                                     mask_or_null(ctx), ctx->g, ctx->c, ctx->partial);
+  else
+    k_totals_partial<ST><<<blocks, kBlock, 0, ctx->stream>>>(static_cast<const store*>(ctx->grid[ctx->cur]),
+                                                            mask_or_null(ctx), ctx->g, ctx->c, ctx->partial);
   LB_HIP(hipGetLastError());
   k_totals_final<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, blocks, ctx->result);
   LB_HIP(hipGetLastError());
@@ -1352,10 +1367,7 @@ lb_status lb_moments(lb_ctx* ctx, double* rho_a, double* rho_b, double* u, int o
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  {
-    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
-    if (lst != LB_OK) return lst;
-  }
+  // moments and totals read the state in either layout, so a read between steps reorders nothing
   const size_t N = static_cast<size_t>(ctx->g.N);
   if (on_device) {
     lb_status st = by_storage(ctx, [&](auto tag) { return moments_impl<decltype(tag)::value>(ctx, rho_a, rho_b, u); });
@@ -1456,10 +1468,6 @@ lb_status lb_totals(lb_ctx* ctx, double out[5], int* nonfinite) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  {
-    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
-    if (lst != LB_OK) return lst;
-  }
   int blocks = blocks_for(ctx->g.N);
   if (blocks > kTotalsMaxBlocks) blocks = kTotalsMaxBlocks;
   lb_status st = by_storage(ctx, [&](auto tag) { return totals_impl<decltype(tag)::value>(ctx, blocks); });

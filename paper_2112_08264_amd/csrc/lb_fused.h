@@ -80,23 +80,6 @@ __device__ __forceinline__ int fused_work_item(int b, int total, int per_round) 
   return base + j * q + (j < r ? j : r) + s;
 }
 
-// ---------------------------------------------------------------------------
-// Tile-major population layout (the fused steps where nx is a multiple of
-// 64 and ny of 4): population plane ki = k Q + i of node (x, y, z) at
-// element
-//   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
-//   tile = (y / 4) (nx / 64) + x / 64,
-// so that one 64 x 4 tile's 38 population rows of one plane are a single
-// contiguous block (77,824 bytes in float64), and a workgroup marching that
-// tile's column reads one stream instead of 38.  Offsets within a plane stay
-// below 2^32 bytes when 38 nx ny times the element size does.
-// ---------------------------------------------------------------------------
-constexpr int kTileX = 64, kTileY = 4, kTileNodes = kTileX * kTileY;
-
-__device__ __forceinline__ long long tile_major_index(int ki, int x, int y, int z, const Geometry& g) {
-  const long long tile = (long long)(y >> 2) * (g.nx >> 6) + (x >> 6);
-  return (long long)z * (2LL * Q * g.nx * g.ny) + (tile * (2 * Q) + ki) * kTileNodes + (y & 3) * kTileX + (x & 63);
-}
 
 // State between the structure-of-arrays layout (plane ki at ki * Npad, node
 // n = x + nx (y + ny z)) and the tile-major one; to_tiled selects the

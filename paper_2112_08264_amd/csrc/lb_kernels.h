@@ -40,20 +40,51 @@ __device__ __forceinline__ void neighbours(int x, int y, int z, const Geometry& 
   for (int i = 0; i < Q; ++i) nb[i] = X[CX[i] + 1] + g.nx * (Y[CY[i] + 1] + g.ny * Z[CZ[i] + 1]);
 }
 
-template <int ST>
+// ---------------------------------------------------------------------------
+// Tile-major population layout (the fused steps where nx is a multiple of
+// 64 and ny of 4): population plane ki = k Q + i of node (x, y, z) at
+// element
+//   z (38 nx ny) + (tile 38 + ki) 256 + (y mod 4) 64 + (x mod 64),
+//   tile = (y / 4) (nx / 64) + x / 64,
+// so that one 64 x 4 tile's 38 population rows of one plane are a single
+// contiguous block (77,824 bytes in float64), and a workgroup marching that
+// tile's column reads one stream instead of 38.  Offsets within a plane stay
+// below 2^32 bytes when 38 nx ny times the element size does.
+// ---------------------------------------------------------------------------
+constexpr int kTileX = 64, kTileY = 4, kTileNodes = kTileX * kTileY;
+
+__device__ __forceinline__ long long tile_major_index(int ki, int x, int y, int z, const Geometry& g) {
+  const long long tile = (long long)(y >> 2) * (g.nx >> 6) + (x >> 6);
+  return (long long)z * (2LL * Q * g.nx * g.ny) + (tile * (2 * Q) + ki) * kTileNodes + (y & 3) * kTileX + (x & 63);
+}
+
+// The 2 x 19 populations of node n, from the structure of arrays or (TILED)
+// the tile-major layout.
+template <int ST, bool TILED = false>
 __device__ __forceinline__ void load_node(const store_t<ST>* __restrict__ f, long long n, const Geometry& g,
                                           const StepCoeffs& c, real_t<ST> (&out)[2][Q]) {
+  if constexpr (TILED) {
+    int x, y, z;
+    node_xyz((int)n, g, x, y, z);
+    const long long t = tile_major_index(0, x, y, z, g);
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[k][i] = decode<ST>(f[(long long)(k * Q + i) * g.Npad + n], c.shift[k][i]);
+      for (int i = 0; i < Q; ++i) out[k][i] = decode<ST>(f[t + (long long)(k * Q + i) * kTileNodes], c.shift[k][i]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[k][i] = decode<ST>(f[(long long)(k * Q + i) * g.Npad + n], c.shift[k][i]);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 1: pseudopotential psi_k of every node (0 at solid nodes).
 // psi is [2][N] in the arithmetic type.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID>
+// TILED: f in the tile-major layout (psi stays indexed by node).
+template <int ST, bool SOLID, bool TILED = false>
 __global__ void __launch_bounds__(kBlock) k_psi(const store_t<ST>* __restrict__ f, real_t<ST>* __restrict__ psi,
                                                 const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c) {
   using real = real_t<ST>;
@@ -61,13 +92,10 @@ __global__ void __launch_bounds__(kBlock) k_psi(const store_t<ST>* __restrict__ 
   if (n >= g.N) return;
   real p[2] = {real(0), real(0)};
   if (!(SOLID && mask[n])) {
+    real v[2][Q];
+    load_node<ST, TILED>(f, n, g, c, v);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      real v[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = decode<ST>(f[(long long)(k * Q + i) * g.Npad + n], c.shift[k][i]);
-      p[k] = pseudopotential(density<real>(v), coef_ref<real>(c));
-    }
+    for (int k = 0; k < 2; ++k) p[k] = pseudopotential(density<real>(v[k]), coef_ref<real>(c));
   }
   psi[n] = p[0];
   psi[(long long)g.N + n] = p[1];
@@ -210,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_check_finite(const double* __restric
 // Moments: rho_A, rho_B and u = (m_A + m_B + (F_A + F_B) / 2) / (rho_A + rho_B).
 // Needs psi of the same state (k_psi).  Outputs are float64; any may be null.
 // ---------------------------------------------------------------------------
-template <int ST, bool SOLID>
+template <int ST, bool SOLID, bool TILED = false>
 __global__ void __launch_bounds__(kBlock) k_moments(const store_t<ST>* __restrict__ f, const real_t<ST>* __restrict__ psi,
                                                     const uint8_t* __restrict__ mask, double* __restrict__ ra,
                                                     double* __restrict__ rb, double* __restrict__ u, Geometry g,
@@ -233,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const store_t<ST>* __restric
   int nb[Q];
   neighbours(x, y, z, g, nb);
   real fv[2][Q];
-  load_node<ST>(f, n, g, c, fv);
+  load_node<ST, TILED>(f, n, g, c, fv);
   real rho[2], m[2][3];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -280,19 +308,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int ST, int NK = 2>  // NK: number of population sets (components)
+// NK: number of population sets (components).  TILED: f in the tile-major
+// layout (two components); nodes are visited in the same order either way,
+// so the totals are the same bits.
+template <int ST, int NK = 2, bool TILED = false>
 __global__ void __launch_bounds__(kBlock) k_totals_partial(const store_t<ST>* __restrict__ f,
                                                            const uint8_t* __restrict__ mask, Geometry g, StepCoeffs c,
                                                            double* __restrict__ partial) {
+  static_assert(!TILED || NK == 2, "the tile-major layout holds both components");
   double acc[kTotals] = {0, 0, 0, 0, 0, 0};
   for (long long n = (long long)blockIdx.x * kBlock + threadIdx.x; n < g.N; n += (long long)gridDim.x * kBlock) {
     if (mask != nullptr && mask[n]) continue;
+    long long t = 0;
+    if constexpr (TILED) {
+      int x, y, z;
+      node_xyz((int)n, g, x, y, z);
+      t = tile_major_index(0, x, y, z, g);
+    }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       double v[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        v[i] = static_cast<double>(decode<ST>(f[(long long)(k * Q + i) * g.Npad + n], c.shift[k][i]));
+        const long long at = TILED ? t + (long long)(k * Q + i) * kTileNodes : (long long)(k * Q + i) * g.Npad + n;
+        v[i] = static_cast<double>(decode<ST>(f[at], c.shift[k][i]));
         if (!(v[i] - v[i] == 0.0)) acc[5] += 1.0;
       }
       acc[k] += density<double>(v);

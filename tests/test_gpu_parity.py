@@ -546,3 +546,45 @@ def test_full_size_tile_major_step_equals_the_structure_of_arrays_step(storage):
         assert torch.equal(mine, snaps[0])
         (_, _, _, _, _), nonfinite = lat.totals()
         assert not nonfinite
+
+
+@pytest.mark.parametrize("storage,shape", [("f64", (5, 8, 64)), ("f64", (3, 12, 128)), ("f32", (6, 12, 64)),
+                                           ("f16s", (7, 8, 128))])
+def test_moments_and_totals_read_the_tile_major_state_in_place(storage, shape):
+    """lb_moments and lb_totals read the state in the order the steps left it
+    (tile-major here), without reordering it: their results equal, bit for
+    bit, those read after lb_get_populations has put the state back in the
+    structure of arrays, and steps taken after such reads continue the same
+    trajectory (float64: bitwise the oracle's)."""
+    torch = _torch()
+    n = int(np.prod(shape))
+    _say(f"case {storage} moments/totals on the tile-major state shape={shape}")
+    a, b = synth.fluid_fields(shape, 0.2, 28)
+    p = O.Params((0.8, 1.1), 3.5)
+    f = torch.empty(2 * 19 * n, dtype=torch.float64, device="cuda")
+
+    def read(lat):
+        ra, rb, u = (torch.empty(k * n, dtype=torch.float64, device="cuda") for k in (1, 1, 3))
+        lat.moments(ra, rb, u)
+        tot, nonfinite = lat.totals()
+        assert not nonfinite
+        return torch.cat([ra, rb, u]), tot
+
+    with P.Lattice(shape, tau=p.tau, G=p.G, storage=storage) as lat:
+        lat.set_fields(a.reshape(-1).copy(), b.reshape(-1).copy())
+        lat.step(3)
+        m_tiled, t_tiled = read(lat)
+        lat.step(1)
+        m_tiled2, t_tiled2 = read(lat)
+        lat.get_populations(f)  # the structure-of-arrays order from here on
+        m_soa, t_soa = read(lat)
+        torch.cuda.synchronize()
+        assert torch.equal(m_tiled2, m_soa)
+        assert t_tiled2 == t_soa
+        assert not torch.equal(m_tiled, m_tiled2)
+        lat.step(1)
+        lat.get_populations(f)
+        torch.cuda.synchronize()
+    if storage == "f64":
+        assert np.array_equal(f.cpu().numpy().reshape((2, 19) + tuple(shape)),
+                              O.step(O.init_equilibrium(a, b), p, n=5))
