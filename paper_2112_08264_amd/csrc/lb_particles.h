@@ -49,7 +49,6 @@
 namespace lbd {
 
 constexpr int kPartThreads = 256;
-constexpr int kLinkChunk = 6;  // directions whose link loads are in flight together (divides 18)
 
 struct PartState {
   double* pos;     // [P][3], in [0, L)
@@ -72,8 +71,13 @@ __device__ __forceinline__ long long pop_index(int ki, int n, int x, int y, int 
 }
 
 // Periodic wrap of any coordinate (a box of a particle whose state has gone
-// non-finite still addresses the lattice).
+// non-finite still addresses the lattice).  A particle's box coordinates lie
+// within one period of the lattice whenever it is at least R + 2 wide, so
+// the remainder is only taken for the others.
 __device__ __forceinline__ int wrap_coord(int c, int L) {
+  if (c >= 0 && c < L) return c;
+  if (c < 0 && c >= -L) return c + L;
+  if (c >= L && c - L < L) return c - L;
   c %= L;
   return c < 0 ? c + L : c;
 }
@@ -104,21 +108,55 @@ __device__ __forceinline__ PartRegs part_regs(const PartState& ps, int p) {
   return q;
 }
 
+// Components of c_i for a direction known only at run time: the tables
+// packed two bits per direction (component + 1).
+constexpr unsigned long long pack_dirs(const int (&c)[Q]) {
+  unsigned long long v = 0;
+  for (int i = 0; i < Q; ++i) v |= (unsigned long long)(c[i] + 1) << (2 * i);
+  return v;
+}
+constexpr unsigned long long kPackedCX = pack_dirs(CX), kPackedCY = pack_dirs(CY), kPackedCZ = pack_dirs(CZ);
+__device__ __forceinline__ int cx_of(int i) { return int((kPackedCX >> (2 * i)) & 3ull) - 1; }
+__device__ __forceinline__ int cy_of(int i) { return int((kPackedCY >> (2 * i)) & 3ull) - 1; }
+__device__ __forceinline__ int cz_of(int i) { return int((kPackedCZ >> (2 * i)) & 3ull) - 1; }
+__device__ __forceinline__ int opp_of(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
 // W_i and the link midpoint r_b (relative to the particle) for the link
-// from fluid node (x, y, z) in direction i into the particle q.
+// from fluid node (x, y, z) in direction i into the particle q.  c_i . u_b
+// is summed in the order of cdot.
 __device__ __forceinline__ double wall_term(int i, int x, int y, int z, double rho, const PartRegs& q,
                                             const Geometry& g, double (&rb)[3]) {
   const double* r = q.r;
   const double* v = q.v;
   const double* w = q.w;
-  rb[0] = fold((double(x) + 0.5 * CX[i]) - r[0], double(g.nx));
-  rb[1] = fold((double(y) + 0.5 * CY[i]) - r[1], double(g.ny));
-  rb[2] = fold((double(z) + 0.5 * CZ[i]) - r[2], double(g.nz));
+  const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+  rb[0] = fold((double(x) + 0.5 * cx) - r[0], double(g.nx));
+  rb[1] = fold((double(y) + 0.5 * cy) - r[1], double(g.ny));
+  rb[2] = fold((double(z) + 0.5 * cz) - r[2], double(g.nz));
   const double ubx = v[0] + (w[1] * rb[2] - w[2] * rb[1]);
   const double uby = v[1] + (w[2] * rb[0] - w[0] * rb[2]);
   const double ubz = v[2] + (w[0] * rb[1] - w[1] * rb[0]);
-  const double cub = cdot<double>(i, ubx, uby, ubz);
+  double cub = 0.0;
+  if (cx == 1) cub = cub + ubx;
+  if (cx == -1) cub = cub - ubx;
+  if (cy == 1) cub = cub + uby;
+  if (cy == -1) cub = cub - uby;
+  if (cz == 1) cub = cub + ubz;
+  if (cz == -1) cub = cub - ubz;
   return (6.0 * weight<double>(i)) * (rho * cub);
+}
+
+// decode / encode for the particle kernels' storages (float64 and float32
+// keep no shift, so a run-time direction needs no table).
+template <int ST>
+__device__ __forceinline__ real_t<ST> decode_dir(store_t<ST> v) {
+  static_assert(ST != ST_F16S, "particles run on float64 and float32 storage");
+  return decode<ST>(v, 0.0f);
+}
+template <int ST>
+__device__ __forceinline__ store_t<ST> encode_dir(real_t<ST> v) {
+  static_assert(ST != ST_F16S, "particles run on float64 and float32 storage");
+  return encode<ST>(v, 0.0f);
 }
 
 // Single-fluid step with particles.  One work-item per node, as k1_step.
@@ -186,6 +224,32 @@ __device__ __forceinline__ int box_node(int b, const int (&lo)[3], int S, const 
   return wrap_coord(cc[0], g.nx) + g.nx * (wrap_coord(cc[1], g.ny) + g.ny * wrap_coord(cc[2], g.nz));
 }
 
+// Box coordinates of the nodes b, b + step, b + 2 step, ... of an S^3 box
+// (b in x-fastest order): the step's own coordinates are added with carries,
+// so only the start takes integer divisions.
+struct BoxWalk {
+  int x, y, z, sx, sy, sz;
+  __device__ __forceinline__ BoxWalk(int b, int step, int S)
+      : x(b % S), y((b / S) % S), z(b / (S * S)), sx(step % S), sy((step / S) % S), sz(step / (S * S)) {}
+  __device__ __forceinline__ void advance(int S) {
+    x += sx;
+    const int cx = x >= S ? 1 : 0;
+    x -= cx * S;
+    y += sy + cx;
+    const int cy = y >= S ? 1 : 0;
+    y -= cy * S;
+    z += sz + cy;
+  }
+};
+
+// box_node for the walker's current node.
+__device__ __forceinline__ int box_node_at(const BoxWalk& w, const int (&lo)[3], const Geometry& g, int (&cc)[3]) {
+  cc[0] = lo[0] + w.x;
+  cc[1] = lo[1] + w.y;
+  cc[2] = lo[2] + w.z;
+  return wrap_coord(cc[0], g.nx) + g.nx * (wrap_coord(cc[1], g.ny) + g.ny * wrap_coord(cc[2], g.nz));
+}
+
 __device__ __forceinline__ void box_origin(const double* r, double R, int (&lo)[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) lo[a] = static_cast<int>(floor(r[a] - R)) - 1;
@@ -216,13 +280,21 @@ __device__ __forceinline__ void part_reduce(double (&acc)[6], double (&red)[4][6
 //
 // Only the shell R - 1.5 <= |d| <= R of the box can hold linked nodes of the
 // particle (a node deeper in has all its neighbours inside).  The shell nodes
-// are queued in LDS in box order, 256 at a time, so that every thread works
-// on one (a seventh or so of the box); thread l takes queue entries
-// l, l + 256, ..., which is the fixed order above.
+// are queued in LDS in box order, 256 at a time.  Each batch of 256 then
+// runs in two phases, so that a thread waits for memory about three times
+// per batch rather than once per chunk of directions:
+//   1. thread l takes queue entry l: its owner, then the owners of its
+//      neighbours outside the particle, all 18 loads at once, give the
+//      node's links; the links are listed in LDS in queue order, directions
+//      ascending (a prefix sum over the workgroup places them);
+//   2. thread l takes list entries l, l + 256, ..., kLinkGroup at a time
+//      with all their loads in flight together, and applies them.
+// Both orders are fixed, so the float64 sums are repeatable.
 //
 // NC components: the populations of component k are planes k Q .. k Q + 18,
 // its recorded densities rho_buf[k N ..]; each link is handled per
 // component, component 0 first.  TILED: fnew is in the tile-major layout.
+constexpr int kLinkGroup = 4;  // links a thread applies with their loads in flight together
 template <int ST, int NC = 1, bool TILED = false>
 __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __restrict__ fnew,
                                                               const int* __restrict__ owner,
@@ -232,6 +304,8 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
   __shared__ double red[4][6];
   __shared__ int queue[2 * kPartThreads];
   __shared__ int wave_count[kPartThreads / 64];
+  __shared__ int node_n[kPartThreads], node_x[kPartThreads], node_y[kPartThreads], node_z[kPartThreads];
+  __shared__ int link_list[kPartThreads * (Q - 1)];  // (queue slot) * 32 + i
   const int p = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const PartRegs q = part_regs(ps, p);
@@ -240,59 +314,111 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
-  // The links of shell node b, directions in chunks of kLinkChunk, in order.
-  // A neighbour x_s - c_i inside this particle (the owner map's own test, on
-  // the same unwrapped coordinates, so the same decision) is solid; only the
-  // others (about a quarter of a shell node's neighbours) load their owner,
-  // the pushed value and their density, all at once.  The registers of one
-  // chunk, not of all 18, stay live.  A direction that is not a link adds
-  // nothing.
-  auto links = [&](int b) {
-    int cc[3];
-    const int n = box_node(b, lo, S, g, cc);
-    if (owner[n] != p) return;
-    const int xs = wrap_coord(cc[0], g.nx), ys = wrap_coord(cc[1], g.ny), zs = wrap_coord(cc[2], g.nz);
+  // exclusive prefix sum of v over the workgroup (thread order); total in `total`
+  auto block_scan = [&](int v, int& total) -> int {
+    int incl = v;
 #pragma unroll
-    for (int i0 = 1; i0 < Q; i0 += kLinkChunk) {
-      int nf[kLinkChunk], of[kLinkChunk];
-      bool outside[kLinkChunk];
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += u;
+    }
+    if (lane == 63) wave_count[wave] = incl;
+    __syncthreads();
+    int base = 0;
+    total = 0;
 #pragma unroll
-      for (int k = 0; k < kLinkChunk; ++k) {
-        const int i = i0 + k;
-        const double ex = double(cc[0] - CX[i]) - q.r[0], ey = double(cc[1] - CY[i]) - q.r[1],
-                     ez = double(cc[2] - CZ[i]) - q.r[2];
-        outside[k] = (ex * ex + ey * ey) + ez * ez > ps.r2;
-        nf[k] = wrap_step(xs - CX[i], g.nx) + g.nx * (wrap_step(ys - CY[i], g.ny) + g.ny * wrap_step(zs - CZ[i], g.nz));
-        of[k] = outside[k] ? owner[nf[k]] : p;  // inside this particle: solid
-      }
+    for (int w = 0; w < kPartThreads / 64; ++w) {
+      base += w < wave ? wave_count[w] : 0;
+      total += wave_count[w];
+    }
+    __syncthreads();  // wave_count is reused by the caller
+    return base + incl - v;
+  };
+
+  // Phase 1 for the first `cnt` queue entries: list their links.  A
+  // neighbour x_s - c_i inside this particle (the owner map's own test, on
+  // the same unwrapped coordinates, so the same decision) is solid; the
+  // others load their owner, and a fluid one makes a link.
+  auto list_links = [&](int cnt) -> int {
+    uint32_t mask = 0;
+    const int t = threadIdx.x;
+    if (t < cnt) {
+      int cc[3];
+      const int n = box_node(queue[t], lo, S, g, cc);
+      if (owner[n] == p) {
+        const int xs = wrap_coord(cc[0], g.nx), ys = wrap_coord(cc[1], g.ny), zs = wrap_coord(cc[2], g.nz);
+        node_n[t] = n;
+        node_x[t] = xs;
+        node_y[t] = ys;
+        node_z[t] = zs;
+        int of[Q];
 #pragma unroll
-      for (int kc = 0; kc < NC; ++kc) {
-        real pushed[kLinkChunk];
-        double rh[kLinkChunk];
-#pragma unroll
-        for (int k = 0; k < kLinkChunk; ++k) {
-          const int i = i0 + k;
-          pushed[k] = real(0);
-          rh[k] = 0.0;
-          if (outside[k]) {
-            pushed[k] = decode<ST>(fnew[pop_index<TILED>(kc * Q + i, n, xs, ys, zs, g)], c.shift[kc][i]);
-            rh[k] = rho_buf[(long long)kc * g.N + nf[k]];
-          }
+        for (int i = 1; i < Q; ++i) {
+          const double ex = double(cc[0] - CX[i]) - q.r[0], ey = double(cc[1] - CY[i]) - q.r[1],
+                       ez = double(cc[2] - CZ[i]) - q.r[2];
+          const bool outside = (ex * ex + ey * ey) + ez * ez > ps.r2;
+          const int nf = wrap_step(xs - CX[i], g.nx) + g.nx * (wrap_step(ys - CY[i], g.ny) + g.ny * wrap_step(zs - CZ[i], g.nz));
+          of[i] = outside ? owner[nf] : p;  // inside this particle: solid
         }
 #pragma unroll
-        for (int k = 0; k < kLinkChunk; ++k) {
-          const int i = i0 + k;
-          if (!owner_fluid(of[k])) continue;
-          const int xf = wrap_step(xs - CX[i], g.nx), yf = wrap_step(ys - CY[i], g.ny), zf = wrap_step(zs - CZ[i], g.nz);
+        for (int i = 1; i < Q; ++i)
+          if (owner_fluid(of[i])) mask |= 1u << i;
+      }
+    }
+    int total = 0;
+    int at = block_scan(__popc(mask), total);
+    while (mask != 0) {
+      const int i = __ffs(mask) - 1;
+      mask &= mask - 1;
+      link_list[at++] = t * 32 + i;
+    }
+    __syncthreads();
+    return total;
+  };
+
+  // Phase 2: apply links j, j + 256, ... of the list.
+  auto apply_links = [&](int total) {
+    for (int j0 = threadIdx.x; j0 < total; j0 += kLinkGroup * kPartThreads) {
+      int n[kLinkGroup], nf[kLinkGroup], dir[kLinkGroup], xs[kLinkGroup], ys[kLinkGroup], zs[kLinkGroup];
+      real pushed[kLinkGroup][NC];
+      double rh[kLinkGroup][NC];
+#pragma unroll
+      for (int u = 0; u < kLinkGroup; ++u) {
+        const int j = j0 + u * kPartThreads;
+        dir[u] = 0;
+        if (j < total) {
+          const int e = link_list[j], s = e >> 5, i = e & 31;
+          dir[u] = i;
+          n[u] = node_n[s];
+          xs[u] = node_x[s];
+          ys[u] = node_y[s];
+          zs[u] = node_z[s];
+          nf[u] = wrap_step(xs[u] - cx_of(i), g.nx) +
+                  g.nx * (wrap_step(ys[u] - cy_of(i), g.ny) + g.ny * wrap_step(zs[u] - cz_of(i), g.nz));
+#pragma unroll
+          for (int kc = 0; kc < NC; ++kc) {
+            pushed[u][kc] = decode_dir<ST>(fnew[pop_index<TILED>(kc * Q + i, n[u], xs[u], ys[u], zs[u], g)]);
+            rh[u][kc] = rho_buf[(long long)kc * g.N + nf[u]];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLinkGroup; ++u) {
+        const int i = dir[u];
+        if (i == 0) continue;
+        const int xf = wrap_step(xs[u] - cx_of(i), g.nx), yf = wrap_step(ys[u] - cy_of(i), g.ny),
+                  zf = wrap_step(zs[u] - cz_of(i), g.nz);
+#pragma unroll
+        for (int kc = 0; kc < NC; ++kc) {
           double rb[3];
-          const double W = wall_term(i, xf, yf, zf, rh[k], q, g, rb);
-          const store_t<ST> back = encode<ST>(pushed[k] - static_cast<real>(W), c.shift[kc][i]);  // w_opp(i) = w_i
-          fnew[pop_index<TILED>(kc * Q + OPP[i], nf[k], xf, yf, zf, g)] = back;
-          fnew[pop_index<TILED>(kc * Q + i, n, xs, ys, zs, g)] = store_t<ST>(0);
-          const double gv = static_cast<double>(decode<ST>(back, c.shift[kc][i]));
+          const double W = wall_term(i, xf, yf, zf, rh[u][kc], q, g, rb);
+          const store_t<ST> back = encode_dir<ST>(pushed[u][kc] - static_cast<real>(W));  // w_opp(i) = w_i
+          fnew[pop_index<TILED>(kc * Q + opp_of(i), nf[u], xf, yf, zf, g)] = back;
+          fnew[pop_index<TILED>(kc * Q + i, n[u], xs[u], ys[u], zs[u], g)] = store_t<ST>(0);
+          const double gv = static_cast<double>(decode_dir<ST>(back));
           const double t = (gv + gv) + W;
-          const double F[3] = {CX[i] == 0 ? 0.0 : (CX[i] > 0 ? t : -t), CY[i] == 0 ? 0.0 : (CY[i] > 0 ? t : -t),
-                               CZ[i] == 0 ? 0.0 : (CZ[i] > 0 ? t : -t)};
+          const double F[3] = {cx_of(i) == 0 ? 0.0 : (cx_of(i) > 0 ? t : -t), cy_of(i) == 0 ? 0.0 : (cy_of(i) > 0 ? t : -t),
+                               cz_of(i) == 0 ? 0.0 : (cz_of(i) > 0 ? t : -t)};
           acc[0] = acc[0] + F[0];
           acc[1] = acc[1] + F[1];
           acc[2] = acc[2] + F[2];
@@ -302,15 +428,17 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
         }
       }
     }
+    __syncthreads();  // the node table and the list are refilled by the next batch
   };
 
   int pending = 0;  // queued shell nodes, the same in every thread (below 256 between rounds)
-  for (int b0 = 0; b0 < nbox; b0 += kPartThreads) {
+  BoxWalk bw(threadIdx.x, kPartThreads, S);
+  for (int b0 = 0; b0 < nbox; b0 += kPartThreads, bw.advance(S)) {
     const int b = b0 + threadIdx.x;
     bool shell = false;
     if (b < nbox) {
       int cc[3];
-      box_node(b, lo, S, g, cc);
+      box_node_at(bw, lo, g, cc);
       const double dx = double(cc[0]) - q.r[0], dy = double(cc[1]) - q.r[1], dz = double(cc[2]) - q.r[2];
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       shell = d2 <= ps.r2 && d2 >= ps.inner2;
@@ -328,14 +456,13 @@ __global__ void __launch_bounds__(kPartThreads) kp_force_move(store_t<ST>* __res
     pending += total;
     __syncthreads();
     if (pending >= kPartThreads) {
-      links(queue[threadIdx.x]);
-      __syncthreads();  // every thread has read its entry
+      apply_links(list_links(kPartThreads));
       if (threadIdx.x < pending - kPartThreads) queue[threadIdx.x] = queue[kPartThreads + threadIdx.x];
       pending -= kPartThreads;
       __syncthreads();
     }
   }
-  if (threadIdx.x < pending) links(queue[threadIdx.x]);
+  if (pending > 0) apply_links(list_links(pending));
   part_reduce(acc, red);
   if (threadIdx.x == 0) {
     const double L[3] = {double(g.nx), double(g.ny), double(g.nz)};
@@ -367,9 +494,10 @@ __global__ void __launch_bounds__(kBlock) kp_owner_scatter(int* __restrict__ own
   int lo[3];
   box_origin(r, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
-  for (int b = threadIdx.x; b < nbox; b += kBlock) {
+  BoxWalk bw(threadIdx.x, kBlock, S);
+  for (int b = threadIdx.x; b < nbox; b += kBlock, bw.advance(S)) {
     int cc[3];
-    const int n = box_node(b, lo, S, g, cc);
+    const int n = box_node_at(bw, lo, g, cc);
     const double dx = double(cc[0]) - r[0], dy = double(cc[1]) - r[1], dz = double(cc[2]) - r[2];
     const double d2 = (dx * dx + dy * dy) + dz * dz;
     if (d2 <= ps.r2) atomicMin(owner + n, p);
@@ -392,9 +520,10 @@ __global__ void __launch_bounds__(kPartThreads) kp_remap(store_t<ST>* __restrict
   box_origin(r, ps.radius, lo);
   const int S = ps.box, nbox = S * S * S;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nbox; b += kPartThreads) {
+  BoxWalk bw(threadIdx.x, kPartThreads, S);
+  for (int b = threadIdx.x; b < nbox; b += kPartThreads, bw.advance(S)) {
     int cc[3];
-    const int n = box_node(b, lo, S, g, cc);
+    const int n = box_node_at(bw, lo, g, cc);
     const bool covered = owner_new[n] == p && owner_fluid(owner_old[n]);
     const bool uncovered = owner_old[n] == p && owner_fluid(owner_new[n]);
     if (!covered && !uncovered) continue;
