@@ -116,10 +116,11 @@ lb_status lb_set_fields(lb_ctx* ctx, const double* rho_a, const double* rho_b,
  * float storage with or without, and the steps with moving particles):
  * the first step after lb_set_fields, lb_set_populations,
  * lb_restore_state, lb_set_particles or a call that needs the structure of
- * arrays (lb_get_populations, lb_save_state to host memory, the two-pass
- * kernel) reorders the grid once, and those calls reorder it back (one
- * read and one write of the grid each).  lb_moments and lb_totals read
- * either order and reorder nothing.  Results do not depend on the order.
+ * arrays (lb_save_state to host memory, the two-pass kernel) reorders the
+ * grid once, and those calls reorder it back (one read and one write of
+ * the grid each).  lb_moments, lb_totals, lb_get_populations and
+ * lb_save_state to device memory read either order and reorder nothing.
+ * Results do not depend on the order.
  * Errors: LB_EINVAL (n < 0), LB_ESTATE (no lb_set_fields /
  * lb_set_populations yet), LB_EDEVICE. */
 lb_status lb_step(lb_ctx* ctx, int32_t n);

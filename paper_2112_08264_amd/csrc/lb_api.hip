@@ -593,8 +593,12 @@ lb_status init_impl(lb_ctx* ctx, const double* ra, const double* rb, const doubl
 template <int ST>
 lb_status decode_impl(lb_ctx* ctx, int plane, double* out) {
   using store = typename StorageTraits<ST>::store_t;
-  k_decode_plane<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
-      static_cast<const store*>(ctx->grid[ctx->cur]), out, mask_or_null(ctx), plane, ctx->g, ctx->c);
+  if (ctx->tiled)  // read in whichever layout the steps left the state
+    k_decode_plane<ST, true><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        static_cast<const store*>(ctx->grid[ctx->cur]), out, mask_or_null(ctx), plane, ctx->g, ctx->c);
+  else
+    k_decode_plane<ST><<<blocks_for(ctx->g.N), kBlock, 0, ctx->stream>>>(
+        static_cast<const store*>(ctx->grid[ctx->cur]), out, mask_or_null(ctx), plane, ctx->g, ctx->c);
   LB_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -1400,10 +1404,6 @@ lb_status lb_get_populations(lb_ctx* ctx, double* f, int on_device) {
   if (!ctx->has_state) return LB_ESTATE;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  {
-    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
-    if (lst != LB_OK) return lst;
-  }
   const size_t N = static_cast<size_t>(ctx->g.N);
   if (!on_device) {
     lb_status st = ensure_plane(ctx);
@@ -1426,10 +1426,6 @@ lb_status lb_set_populations(lb_ctx* ctx, const double* f, int on_device) {
   if (ctx == nullptr || f == nullptr) return LB_EINVAL;
   DeviceGuard dg(ctx->p.device);
   if (!dg.ok) return LB_EDEVICE;
-  {
-    lb_status lst = set_layout(ctx, false);  // the structure-of-arrays layout for everything but the step
-    if (lst != LB_OK) return lst;
-  }
   const size_t N = static_cast<size_t>(ctx->g.N);
   lb_status st = ensure_plane(ctx);
   if (st != LB_OK) return st;
@@ -1449,6 +1445,7 @@ lb_status lb_set_populations(lb_ctx* ctx, const double* f, int on_device) {
   LB_HIP(hipStreamSynchronize(ctx->stream));
   if (bad) return LB_EINVAL;
   if (!ctx->has_state) LB_HIP(hipMemsetAsync(ctx->grid[ctx->cur ^ 1], 0, ctx->grid_bytes, ctx->stream));
+  ctx->tiled = false;  // every plane is written below, in the structure of arrays: the old state needs no reorder
   for (int plane = 0; plane < 2 * Q; ++plane) {
     const double* src = f + plane * N;
     if (!on_device) {

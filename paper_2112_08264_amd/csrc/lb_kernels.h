@@ -201,14 +201,22 @@ __global__ void __launch_bounds__(kBlock) k_validate_fields(const double* __rest
 // ---------------------------------------------------------------------------
 // Solid nodes export 0 whatever their stored bits (a float16 offset would
 // otherwise decode a stored 0 as w_i rho0).
-template <int ST>
+// One population plane as float64 (zero at solid nodes), from the structure
+// of arrays or (TILED) the tile-major layout.
+template <int ST, bool TILED = false>
 __global__ void __launch_bounds__(kBlock) k_decode_plane(const store_t<ST>* __restrict__ f, double* __restrict__ out,
                                                          const uint8_t* __restrict__ mask, int plane, Geometry g,
                                                          StepCoeffs c) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= g.N) return;
   const int k = plane / Q, i = plane % Q;
-  double v = static_cast<double>(decode<ST>(f[(long long)plane * g.Npad + n], c.shift[k][i]));
+  long long at = (long long)plane * g.Npad + n;
+  if constexpr (TILED) {
+    int x, y, z;
+    node_xyz(n, g, x, y, z);
+    at = tile_major_index(plane, x, y, z, g);
+  }
+  double v = static_cast<double>(decode<ST>(f[at], c.shift[k][i]));
   if (mask != nullptr && mask[n]) v = 0.0;
   out[n] = v;
 }

@@ -550,12 +550,12 @@ def test_full_size_tile_major_step_equals_the_structure_of_arrays_step(storage):
 
 @pytest.mark.parametrize("storage,shape", [("f64", (5, 8, 64)), ("f64", (3, 12, 128)), ("f32", (6, 12, 64)),
                                            ("f16s", (7, 8, 128))])
-def test_moments_and_totals_read_the_tile_major_state_in_place(storage, shape):
-    """lb_moments and lb_totals read the state in the order the steps left it
-    (tile-major here), without reordering it: their results equal, bit for
-    bit, those read after lb_get_populations has put the state back in the
-    structure of arrays, and steps taken after such reads continue the same
-    trajectory (float64: bitwise the oracle's)."""
+def test_reads_of_the_tile_major_state_in_place(storage, shape):
+    """lb_moments, lb_totals and lb_get_populations read the state in the
+    order the steps left it (tile-major here), without reordering it: their
+    results equal, bit for bit, those read after a host snapshot has put the
+    state back in the structure of arrays, and steps taken after such reads
+    continue the same trajectory (float64: bitwise the oracle's)."""
     torch = _torch()
     n = int(np.prod(shape))
     _say(f"case {storage} moments/totals on the tile-major state shape={shape}")
@@ -576,11 +576,16 @@ def test_moments_and_totals_read_the_tile_major_state_in_place(storage, shape):
         m_tiled, t_tiled = read(lat)
         lat.step(1)
         m_tiled2, t_tiled2 = read(lat)
-        lat.get_populations(f)  # the structure-of-arrays order from here on
+        g_tiled = torch.empty_like(f)
+        lat.get_populations(g_tiled)
+        host = np.empty(int(P.lb_state_bytes(lat.ctx)), dtype=np.uint8)
+        P.lb_save_state(lat.ctx, host)  # a host snapshot: the structure-of-arrays order from here on
         m_soa, t_soa = read(lat)
+        lat.get_populations(f)
         torch.cuda.synchronize()
         assert torch.equal(m_tiled2, m_soa)
         assert t_tiled2 == t_soa
+        assert torch.equal(g_tiled, f)
         assert not torch.equal(m_tiled, m_tiled2)
         lat.step(1)
         lat.get_populations(f)
