@@ -22,7 +22,7 @@
 // come either from a record the forward step wrote or from k_adj_moments.
 #pragma once
 
-#include "lb_kernels.h"
+#include "lb_fused.h"
 
 namespace lbd {
 
@@ -234,6 +234,107 @@ __global__ void __launch_bounds__(kBlock) k_adj_r(const real_t<ST>* __restrict__
     }
     const real rho = mom[(long long)k * g.N + n];
     r[(long long)k * g.N + n] = -exp_real<real>(-rho / ref) * T;
+  }
+}
+
+// The same stencil term as k_adj_r, by a z-march over 64 x 4 tiles (nx a
+// multiple of 64, ny of 4): W of the planes z - 1 .. z + 2 with a one-node
+// halo sit in an LDS ring, so each W value comes from HBM about once instead
+// of being gathered from the cache by up to 18 neighbours.  The loads of
+// plane z + 2 are issued before plane z is computed and written to the ring
+// after it, with one barrier per plane.  Every node sums the same terms in
+// the same order as k_adj_r, so the two give the same bits.
+template <int ST>
+__global__ void __launch_bounds__(256) k_adj_r_march(const real_t<ST>* __restrict__ mom,
+                                                     const real_t<ST>* __restrict__ Win,
+                                                     const uint8_t* __restrict__ mask, real_t<ST>* __restrict__ r,
+                                                     Geometry g, StepCoeffs c, FusedTiling t) {
+  using real = real_t<ST>;
+  constexpr int TX = 64, TY = 4, RX = TX + 2, RY = TY + 2, NS = 4;
+  constexpr int NH = 2 * RX + 2 * TY;  // halo nodes of a plane (140 < 256 threads)
+  __shared__ real ring[NS][6][RY][RX];
+  const int w = fused_work_item(blockIdx.x, t.total, t.per_round);
+  const int chunk = w / (t.tiles_x * t.tiles_y);
+  const int tile = w - chunk * (t.tiles_x * t.tiles_y);
+  const int ty0 = (tile / t.tiles_x) * TY, tx0 = (tile % t.tiles_x) * TX;
+  const int z0 = chunk * t.chunk;
+  const int zlen = min(t.chunk, g.nz - z0);
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int gx = tx0 + lx, gy = ty0 + ly;  // the host checks nx % 64 == 0 and ny % 4 == 0
+  const long long N = g.N;
+  const uint32_t plane_n = (uint32_t)g.nx * (uint32_t)g.ny;
+  const uint32_t row = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy;
+  // halo node of this thread: rows -1 and TY (with the corners), then columns -1 and TX
+  const bool has_halo = threadIdx.x < NH;
+  int hx = 0, hy = 0;
+  if (threadIdx.x < 2 * RX) {
+    hy = threadIdx.x < RX ? -1 : TY;
+    hx = (threadIdx.x % RX) - 1;
+  } else if (has_halo) {
+    const int cn = threadIdx.x - 2 * RX;
+    hx = (cn & 1) ? TX : -1;
+    hy = cn >> 1;
+  }
+  const int hgx = ((tx0 + hx) % g.nx + g.nx) % g.nx, hgy = ((ty0 + hy) % g.ny + g.ny) % g.ny;
+  const uint32_t hrow = (uint32_t)hgx + (uint32_t)g.nx * (uint32_t)hgy;
+  auto wrapz = [&](int z) { return z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z); };
+  auto slot = [&](int z) { return (z - z0 + 1 + NS) % NS; };  // ring slot of plane z (z0 - 1 .. z0 + zlen)
+
+  real iw[6], hw[6];
+  auto load = [&](int z) {  // W of plane z (interior node and halo node of this thread) into registers
+    const long long zo = (long long)plane_n * wrapz(z);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) iw[v] = Win[(long long)v * N + zo + row];
+    if (has_halo)
+#pragma unroll
+      for (int v = 0; v < 6; ++v) hw[v] = Win[(long long)v * N + zo + hrow];
+  };
+  auto store = [&](int z) {  // ... into the ring
+    const int s = slot(z);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) ring[s][v][ly + 1][lx + 1] = iw[v];
+    if (has_halo)
+#pragma unroll
+      for (int v = 0; v < 6; ++v) ring[s][v][hy + 1][hx + 1] = hw[v];
+  };
+  load(z0 - 1);
+  store(z0 - 1);
+  load(z0);
+  store(z0);
+  load(z0 + 1);
+  store(z0 + 1);
+  __syncthreads();
+  const real ref = coef_ref<real>(c);
+  for (int j = 0; j < zlen; ++j) {
+    const int z = z0 + j;
+    if (j + 2 <= zlen) load(z + 2);  // plane z0 + zlen is the chunk's far neighbour
+    const long long n = (long long)plane_n * z + row;
+    const int sm = slot(z - 1), s0 = slot(z), sp = slot(z + 1);
+    if (mask != nullptr && mask[n]) {
+      r[n] = real(0);
+      r[N + n] = real(0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int kb = 1 - k;
+        real T = real(0);
+#pragma unroll
+        for (int l = 1; l < Q; ++l) {
+          // W at x - c_l
+          const int si = CZ[l] > 0 ? sm : (CZ[l] < 0 ? sp : s0);
+          const int yy = ly + 1 - CY[l], xx = lx + 1 - CX[l];
+          real cw = real(0);
+          if (CX[l] != 0) cw = cw + real(CX[l]) * ring[si][3 * kb + 0][yy][xx];
+          if (CY[l] != 0) cw = cw + real(CY[l]) * ring[si][3 * kb + 1][yy][xx];
+          if (CZ[l] != 0) cw = cw + real(CZ[l]) * ring[si][3 * kb + 2][yy][xx];
+          T += weight<real>(l) * cw;
+        }
+        const real rho = mom[(long long)k * N + n];
+        r[(long long)k * N + n] = -exp_real<real>(-rho / ref) * T;
+      }
+    }
+    if (j + 2 <= zlen) store(z + 2);
+    __syncthreads();
   }
 }
 

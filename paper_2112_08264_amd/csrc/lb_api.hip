@@ -62,6 +62,14 @@ constexpr int kFloatDepth = 2;
 // 256^3 against 64 x 8 tiles with one iteration of lead.  float16-shifted
 // went the other way (0.729 -> 0.794 ms) and keeps the 64 x 8 tiles.
 constexpr int kFloat32Lead = 2;
+// Adjoint stencil march: columns in chunks of at least kAdjMarchMinChunk
+// planes (each chunk re-reads the two planes beside it), enough chunks for
+// kAdjMarchWGs workgroups per compute unit.  At 128^3 (8-plane chunks, four
+// workgroups per CU) the backward pass took 189 instead of 192 ms (float32)
+// and 398 instead of 410 ms (float64) against the per-node gather; 32-plane
+// chunks, one workgroup per CU, made float32 slower (200 ms).
+constexpr int kAdjMarchMinChunk = 8;
+constexpr int kAdjMarchWGs = 4;
 // Staged float64 step on 64 x 4 tiles (two waves per row) where nx allows:
 // 9% faster than 32 x 8 at 256^3 -- half as many tile edges in x, where a
 // push store writes a 128-byte line only in part.  The unstaged kernel was
@@ -119,6 +127,8 @@ struct lb_ctx {
   FusedTiling tiling_cg{};    // float32 colour-gradient kernel (64 x 4 tiles)
   FusedTiling tiling_tall{};  // float Shan-Chen kernel without solids (64 x 8 tiles)
   bool tall = false;          // tiling_tall is used (its chunks hold >= kFloatTallMinChunk planes)
+  FusedTiling tiling_adj{};   // z-marching adjoint stencil kernel (64 x 4 tiles)
+  bool adj_march = false;     // k_adj_r_march runs the adjoint stencil term (nx % 64 == 0, ny % 4 == 0)
   int64_t bytes = 0;
   // moving particles (lb_set_particles, colour-gradient model)
   int np = 0;
@@ -734,7 +744,14 @@ lb_status adjoint_record_step_impl(lb_ctx* ctx, const typename StorageTraits<ST>
     k_adj_local<ST><<<nb, kBlock, 0, ctx->stream>>>(lin, r, lout, mom, m, W, ctx->adj_partial, ctx->g, ctx->c);
   });
   if (st != LB_OK) return st;
-  st = launch(ctx, SLOT_ADJ_R, [&] { k_adj_r<ST><<<nb, kBlock, 0, ctx->stream>>>(mom, W, m, r, ctx->g, ctx->c); });
+  st = launch(ctx, SLOT_ADJ_R, [&] {
+    if (ctx->adj_march) {
+      const FusedTiling t = ctx->tiling_adj;
+      k_adj_r_march<ST><<<dim3(t.total), dim3(256), 0, ctx->stream>>>(mom, W, m, r, ctx->g, ctx->c, t);
+    } else {
+      k_adj_r<ST><<<nb, kBlock, 0, ctx->stream>>>(mom, W, m, r, ctx->g, ctx->c);
+    }
+  });
   if (st != LB_OK) return st;
   ctx->lam_cur ^= 1;
   return LB_OK;
@@ -1133,9 +1150,10 @@ const char* lb_timing_name(int32_t slot) {
 // they ran 22% faster than whole 512-plane columns.
 // chunk_full_round: also use 64-plane chunks when the columns fill exactly
 // one round (the unstaged component-pair kernel of the float32 colour-gradient
-// step runs 17% faster so at 256^3).
+// step runs 17% faster so at 256^3).  min_chunk: the shortest chunk (or the
+// whole column where it is shorter).
 bool make_tiling(const lb_params& p, int tile_x, int tile_y, int cus, FusedTiling* out,
-                 bool chunk_full_round = false) {
+                 bool chunk_full_round = false, int min_chunk = 4) {
   FusedTiling t{};
   t.tiles_x = (p.nx + tile_x - 1) / tile_x;
   t.tiles_y = (p.ny + tile_y - 1) / tile_y;
@@ -1145,7 +1163,7 @@ bool make_tiling(const lb_params& p, int tile_x, int tile_y, int cus, FusedTilin
   if (cols > target || (chunk_full_round && cols == target)) want = p.nz / 64;
   if (want < 1) want = 1;
   int chunk = static_cast<int>((p.nz + want - 1) / want);
-  if (chunk < 4) chunk = 4;
+  if (chunk < min_chunk) chunk = min_chunk;
   if (chunk > p.nz) chunk = p.nz;
   t.chunk = chunk;
   t.chunks = (p.nz + chunk - 1) / chunk;
@@ -1227,6 +1245,8 @@ lb_status lb_create(const lb_params* params, lb_ctx** out) {
       delete ctx;
       return LB_EINVAL;
     }
+    if (p.nx % kTileX == 0 && p.ny % kTileY == 0)
+      ctx->adj_march = make_tiling(p, kTileX, kTileY, kAdjMarchWGs * cus, &ctx->tiling_adj, false, kAdjMarchMinChunk);
   }
   c.Gf = static_cast<float>(p.G);
   c.psi_reff = static_cast<float>(p.psi_ref);

@@ -37,17 +37,19 @@ def _state(shape, seed, amp=0.3, solid=None):
     return f
 
 
+# (5, 6, 7): the per-node stencil kernel; (6, 8, 64) and (4, 4, 128): the z-marching one (nx a multiple of 64,
+# ny of 4), one tile whose halo wraps onto itself and two tiles in x
+@pytest.mark.parametrize("shape", [(5, 6, 7), (6, 8, 64), (4, 4, 128)])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 2e-4)])
 @pytest.mark.parametrize("with_solid", [False, True])
-def test_adjoint_steps_match_oracle(storage, tol, with_solid):
+def test_adjoint_steps_match_oracle(storage, tol, with_solid, shape):
     torch = _torch()
-    shape = (5, 6, 7)
     n = int(np.prod(shape))
     solid = None
     if with_solid:
         solid = np.zeros(shape, np.uint8)
-        solid[1, 2, 3] = solid[2, 2, 3] = solid[3, 4, 1] = 1
-    _say(f"case adjoint steps {storage} solid={with_solid}")
+        solid[1, 2, 3] = solid[2, 2, 3] = solid[3, min(4, shape[1] - 1), 1] = 1
+    _say(f"case adjoint steps {storage} solid={with_solid} shape={shape}")
     p = O.Params((0.8, 1.3), 3.5)
     states = [_state(shape, 10 + t, solid=solid) for t in range(3)]
     rng = np.random.default_rng(3)
