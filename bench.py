@@ -728,7 +728,7 @@ PROFILE_TARGETS = {
     "single_f32": ("case1_256_f32", {"k1_step": "k1_step<"}),
     "single_f64": ("case1_256_f64", {"k1_step": "k1_step<"}),
     "spheres_f32": ("spheres512_f32", {"fused": "k_fused<"}),
-    "adjoint_f32": ("adjoint128_f32", {"adj_local": "k_adj_local<", "adj_r": "k_adj_r<"}),
+    "adjoint_f32": ("adjoint128_f32", {"adj_local": "k_adj_local<", "adj_r": "k_adj_r_march<"}),
     "particles_f32": ("case3c_256_f32", {"k1p_step": "k1p_step<", "force_move": "kp_force_move<"}),
     "cgp_f32": ("case3cg_c_256_f32", {"fused": "k_fused_pair<", "force_move": "kp_force_move<"}),
 }
